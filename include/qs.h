@@ -1,0 +1,263 @@
+/*
+ * qs.h -- C ABI of the MI355X (gfx950) state-vector library.
+ *
+ * The library updates a 2^n complex state vector on one GPU: gate-level
+ * sweeps (Sec. II of Haener et al., "High Performance Emulation of Quantum
+ * Circuits"), fused k-qubit blocks, and the emulator shortcuts of Sec. III:
+ * the QFT as an in-place FFT (Sec. III-B), arithmetic as a permutation of
+ * basis states (Sec. III-A), and measurement quantities read directly off
+ * the state (Sec. III-D).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State layout. Amplitude i (0 <= i < 2^n) is the coefficient of basis state
+ *   |i>; qubit q is bit q of i (qubit 0 = least significant bit). The paper's
+ *   Kronecker example (Sec. II) writes qubit 0 as the most significant factor;
+ *   relabel q -> n-1-q to go from one to the other. Amplitudes are stored
+ *   contiguously, (re, im) interleaved: QS_C128 = two doubles (16 B),
+ *   QS_C64 = two floats (8 B). The buffer is at least 256-byte aligned.
+ *
+ * Gate matrices. A gate on k targets is a 2^k x 2^k complex matrix M given in
+ *   FP64, row-major, (re, im) interleaved (2^(2k+1) doubles). Bit m of the
+ *   local index is the bit of qubit targets[m]; on every group of 2^k
+ *   amplitudes that agree outside the targets the gate computes
+ *   out_j = sum_l M[j][l] * in_l (Sec. II: the 2^n x 2^n operator is the
+ *   Kronecker product of M with identities). Table 1's two-qubit gates list
+ *   the control as the more significant local bit, so CNOT(c -> t) is given
+ *   as targets = {t, c}. ctrl_mask/ctrl_vals restrict the gate to indices i
+ *   with (i & ctrl_mask) == ctrl_vals. QS_C64 states receive the FP64 matrix
+ *   and cast it to FP32 on the device.
+ *
+ * Ownership. The caller owns every host array it passes (targets, matrices,
+ *   uniforms, outputs); the library copies what it needs before returning, so
+ *   they may be freed or reused at once. State memory is either allocated by
+ *   the library (device_buf == NULL in qs_alloc) or borrowed from the caller
+ *   (e.g. a torch tensor's data pointer), in which case the caller keeps it
+ *   alive until qs_free.
+ *
+ * Streams and synchronisation. Every device operation of a handle is
+ *   enqueued on the handle's HIP stream. Gate, program and emulation calls
+ *   return once enqueued. Calls that produce host results (qs_norm2,
+ *   qs_expectation, qs_measure, qs_get_state) and qs_sync wait for the stream.
+ *
+ * Errors. Every entry point returns a qs_status. Arguments are validated
+ *   before anything is enqueued, so on QS_EINVAL / QS_EUNSUPPORTED /
+ *   QS_ENOMEM the state is unchanged. Asynchronous device faults surface as
+ *   QS_EDEVICE at the next synchronising call. qs_last_error() returns a
+ *   message for the calling thread's last failure. Nothing throws across the
+ *   ABI.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qs_state *qs_handle;
+typedef struct qs_program_t *qs_program;
+
+enum qs_dtype { QS_C64 = 0, QS_C128 = 1 };
+
+enum qs_status {
+    QS_OK = 0,
+    QS_EINVAL = 1,        /* bad argument */
+    QS_ENOMEM = 2,        /* device or host allocation failed */
+    QS_EDEVICE = 3,       /* HIP runtime or kernel failure */
+    QS_EUNSUPPORTED = 4,  /* valid request this build does not implement */
+    QS_ENOTUNITARY = 5    /* matrix failed the optional unitarity check */
+};
+
+/* Largest qubit count a handle accepts (2^34 complex128 = 256 GiB). */
+#define QS_MAX_QUBITS 34
+/* Largest fused-block / gate width accepted by the sweep kernels. */
+#define QS_MAX_K 6
+
+/* Message describing the calling thread's last failed call ("" if none). */
+const char *qs_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int qs_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* State lifetime (Sec. II: 2^n complex amplitudes, sum |alpha_i|^2 = 1)    */
+/* ---------------------------------------------------------------------- */
+
+/* Create a handle for an n-qubit state (1 <= n <= QS_MAX_QUBITS) of the given
+ * dtype on the current HIP device. device_buf == NULL: the library allocates
+ * 2^n amplitudes and sets |0...0>. device_buf != NULL: the caller's buffer
+ * (>= 2^n amplitudes, 256-byte aligned) is used as is, contents untouched.
+ * hip_stream: a hipStream_t (NULL = the null stream). */
+int qs_alloc(int n_qubits, int dtype, void *device_buf, void *hip_stream, qs_handle *out);
+
+/* Release the handle and whatever the library allocated for it; waits for
+ * the handle's stream first. A borrowed buffer is not freed. */
+int qs_free(qs_handle h);
+
+/* n, dtype and the device address that currently holds the state (it can
+ * change after an out-of-place emulation on a library-owned state). */
+int qs_info(qs_handle h, int *n_qubits, int *dtype, void **device_ptr);
+
+/* Set the state to |0...0>. */
+int qs_set_zero(qs_handle h);
+
+/* Copy the whole state to / from host memory (2^n amplitudes of the
+ * handle's dtype). Both wait for the stream. */
+int qs_get_state(qs_handle h, void *host_dst);
+int qs_set_state(qs_handle h, const void *host_src);
+
+/* Copy the amplitudes at `count` indices (each < 2^n) to host_dst (count
+ * amplitudes of the handle's dtype). For spot checks of large states
+ * without a full copy. Waits for the stream. */
+int qs_get_amplitudes(qs_handle h, int count, const uint64_t *indices, void *host_dst);
+
+/* Wait for all work enqueued on the handle; reports deferred device faults. */
+int qs_sync(qs_handle h);
+
+/* ---------------------------------------------------------------------- */
+/* Gates (Sec. II, Table 1)                                                */
+/* ---------------------------------------------------------------------- */
+
+/* Apply one gate on k targets (1 <= k <= QS_MAX_K), see "Gate matrices".
+ * The matrix is classified on the host and the cheapest exact sweep is
+ * chosen (Sec. II: skip multiplications by one and zero; Sec. III-B: a
+ * conditional phase shift touches only a quarter of the vector):
+ *   identity          -> nothing enqueued;
+ *   diagonal, one entry != 1 -> multiply only the indices carrying it;
+ *   diagonal          -> one elementwise multiply pass;
+ *   monomial (one nonzero per row and column) -> move amplitudes, multiply
+ *                        only where the entry is not exactly 1 (moves of
+ *                        permutation gates are bit-exact);
+ *   otherwise         -> dense group sweep.
+ * Errors: QS_EINVAL for k out of range, duplicate or out-of-range targets,
+ * controls overlapping targets, ctrl_vals outside ctrl_mask, NULL pointers. */
+int qs_apply_gate(qs_handle h, int k, const int *targets, const double *matrix,
+                  uint64_t ctrl_mask, uint64_t ctrl_vals);
+
+/* Apply a sequence of already fused dense blocks in order: block b acts on
+ * k_per_block[b] targets taken consecutively from targets_concat with its
+ * matrix taken consecutively from matrices_concat (same layout as
+ * qs_apply_gate, no controls). Equivalent to n_blocks qs_apply_gate calls. */
+int qs_apply_fused(qs_handle h, int n_blocks, const int *k_per_block,
+                   const int *targets_concat, const double *matrices_concat);
+
+/* ---------------------------------------------------------------------- */
+/* Circuits, fusion planning and compiled programs                         */
+/* ---------------------------------------------------------------------- */
+
+/* A gate list in circuit order (same per-gate layout as qs_apply_gate).
+ * ctrl_mask / ctrl_vals may be NULL (no controls). */
+typedef struct qs_circuit {
+    int n_gates;
+    const int *k;              /* [n_gates] */
+    const int *targets;        /* concatenated, sum(k) entries */
+    const double *matrices;    /* concatenated, sum(2^(2k+1)) doubles */
+    const uint64_t *ctrl_mask; /* [n_gates] or NULL */
+    const uint64_t *ctrl_vals; /* [n_gates] or NULL */
+} qs_circuit;
+
+/* Host-only greedy fusion plan: gates are grouped into blocks acting on at
+ * most max_k distinct qubits (targets and controls together); a gate joins
+ * the open block only if it commutes past every gate skipped so far (no
+ * shared qubit), so applying the blocks in order equals applying the gates
+ * in order. Outputs (caller-allocated): *n_blocks; block_of_gate[n_gates];
+ * block_k[n_gates] (qubit count of each block, first *n_blocks used);
+ * block_qubits[n_gates * QS_MAX_K] (ascending qubits of block b at
+ * b*QS_MAX_K). A gate wider than max_k forms a block of its own. Runs
+ * without a GPU. */
+int qs_plan_fusion(const qs_circuit *c, int n_qubits, int max_k, int *n_blocks,
+                   int *block_of_gate, int *block_k, int *block_qubits);
+
+/* Plan (as qs_plan_fusion) and compose on the GPU, in FP64, the matrix of
+ * every block: the ordered product of the block's gates embedded in the
+ * block's 2^k space. Blocks whose gates are all diagonal are kept diagonal.
+ * The program holds device copies of everything it needs and can be run on
+ * any handle of the same qubit count, any number of times. */
+int qs_compile(qs_handle h, const qs_circuit *c, int max_k, qs_program *out);
+
+/* Number of blocks and, if block_k != NULL, their widths; bytes_per_run:
+ * algorithmic HBM bytes one run moves for the handle's dtype (read + write of
+ * every amplitude each block touches). */
+int qs_program_info(qs_program p, int *n_blocks, int *block_k, double *bytes_per_run);
+
+/* Copy the composed FP64 matrix of block b (2^(2k+1) doubles) and its
+ * ascending qubit list (k ints) to the host. */
+int qs_program_block(qs_program p, int b, double *matrix_out, int *qubits_out);
+
+/* Enqueue one run of the program on the handle. */
+int qs_run_program(qs_handle h, qs_program p);
+
+int qs_program_free(qs_program p);
+
+/* Compile with max_k, run once, free. */
+int qs_apply_circuit(qs_handle h, const qs_circuit *c, int max_k);
+
+/* ---------------------------------------------------------------------- */
+/* Emulation: QFT as an FFT (Sec. III-B)                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Replace the field of m qubits [q_lo, q_lo+m) by its QFT:
+ *   alpha_l -> 2^(-m/2) sum_k alpha_k exp(+2 pi i k l / 2^m),
+ * with the other index bits as spectators and the output in natural order;
+ * inverse != 0 uses exp(-2 pi i k l / 2^m). Requires 1 <= m and
+ * q_lo + m <= n. The result is the gate-level circuit's (Hadamards,
+ * conditional phase shifts and the final SWAPs) up to rounding. */
+int qs_emulate_qft(qs_handle h, int q_lo, int m, int inverse);
+
+/* ---------------------------------------------------------------------- */
+/* Emulation: arithmetic as a permutation of basis states (Sec. III-A)     */
+/* ---------------------------------------------------------------------- */
+
+enum qs_perm_kind { QS_PERM_MODMUL = 0, QS_PERM_TABLE = 1 };
+
+typedef struct qs_perm {
+    int kind;
+    /* QS_PERM_MODMUL: |c>|x> -> |c>|a^c x mod N> for x < N, x >= N fixed.
+     * x is the w-bit field at work_lo, c the c-bit field at ctrl_lo (c may
+     * be 0: plain x -> a x mod N). Requires 2 <= N <= 2^w, N < 2^32,
+     * gcd(a, N) = 1, disjoint fields inside the state. */
+    int work_lo, w, ctrl_lo, c;
+    uint64_t a, N;
+    /* QS_PERM_TABLE: the nbits-wide field at lo moves from value f to
+     * dest[f] (dest: 2^nbits entries, a permutation of 0..2^nbits-1,
+     * nbits <= 24). */
+    int lo, nbits;
+    const uint64_t *dest;
+} qs_perm;
+
+/* Apply the permutation; amplitudes move bit-exactly. Out of place through
+ * a library scratch state of the same size (allocated on first use); a
+ * borrowed state buffer is refreshed from it, a library-owned one is
+ * swapped with it (see qs_info). QS_EINVAL if a table is not a permutation
+ * or gcd(a, N) != 1. */
+int qs_emulate_permutation(qs_handle h, const qs_perm *p);
+
+/* ---------------------------------------------------------------------- */
+/* Measurement quantities (Sec. III-D, Sec. II)                            */
+/* ---------------------------------------------------------------------- */
+
+/* sum_i |alpha_i|^2, accumulated in FP64. */
+int qs_norm2(qs_handle h, double *out);
+
+/* <psi|P|psi> for the Pauli string with X on x_mask, Y on y_mask, Z on
+ * z_mask (disjoint masks), accumulated in FP64. */
+int qs_expectation(qs_handle h, uint64_t x_mask, uint64_t y_mask, uint64_t z_mask,
+                   double *out_re, double *out_im);
+
+/* Measure m qubits (1 <= m <= 20, distinct): computes the marginal
+ * probabilities p[o] (bit r of o = qubit qubits[r]); for each of `shots`
+ * caller-supplied uniforms u in [0,1) returns the smallest o whose running
+ * sum of p exceeds u * sum(p). probs_or_null receives p (2^m doubles) if
+ * not NULL. collapse != 0 (requires shots >= 1) projects the state onto the
+ * first shot's outcome and renormalises. */
+int qs_measure(qs_handle h, int m, const int *qubits, int shots, const double *uniforms,
+               uint64_t *outcomes, double *probs_or_null, int collapse);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

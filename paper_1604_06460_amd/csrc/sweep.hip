@@ -1,0 +1,530 @@
+// Gate sweeps over a 2^n state (Sec. II): the 2^n x 2^n operator of a k-qubit
+// gate is the Kronecker product of its 2^k x 2^k matrix with identities, so a
+// sweep visits every group of 2^k amplitudes that agree outside the targets
+// and multiplies it by the small matrix. Structure is exploited as Sec. II
+// and Sec. III-B describe: multiplications by one and zero are skipped, a
+// conditional phase shift touches only the indices that carry the phase,
+// and permutation gates only move amplitudes.
+//
+// Index mapping. The "fixed" bit positions of a sweep (targets, and control
+// qubits whose value is pinned) are removed from the index space; a work
+// item g in [0, 2^(n - nfix)) is expanded back by inserting a zero at every
+// fixed position (ascending) and OR-ing the pinned control values. Lanes of a
+// wave take consecutive g, so they walk the lowest free bits and global
+// accesses coalesce whenever no target sits in the lowest bits.
+#include "qs_internal.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace qs {
+namespace {
+
+constexpr int kMaxFix = 40;
+constexpr int kBlock = 256;
+
+struct FixArgs {
+    int nfix;
+    int pos[kMaxFix];  // ascending
+    uint64_t vals;     // pinned bits OR-ed after expansion
+};
+
+template <int D>
+struct OffArgs {
+    uint64_t o[D];     // offset of local index j inside a group
+};
+
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+template <typename IT>
+__device__ __forceinline__ IT expand(IT g, const FixArgs &f)
+{
+    for (int i = 0; i < f.nfix; ++i) {
+        const int p = f.pos[i];
+        const IT lo = g & ((IT(1) << p) - IT(1));
+        g = ((g >> p) << (p + 1)) | lo;
+    }
+    return g | IT(f.vals);
+}
+
+// Dense sweep: one thread owns one group, holds its 2^K amplitudes in
+// registers and writes out_j = sum_l M[j][l] in_l. The matrix pointer and
+// every index into it are uniform, so the entries are read through scalar
+// loads and used as SGPR operands of the FMAs.
+template <typename R, int K, typename IT>
+__global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict__ psi,
+                                                  const R *__restrict__ mat, IT n_groups,
+                                                  FixArgs fx, OffArgs<(1 << K)> off)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K;
+    const IT stride = IT(gridDim.x) * kBlock;
+    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_groups; g += stride) {
+        C2 *p = psi + expand<IT>(g, fx);
+        C2 v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = p[off.o[j]];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            R re = R(0), im = R(0);
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                const R mr = mat[2 * (j * D + l)];
+                const R mi = mat[2 * (j * D + l) + 1];
+                re = fma(mr, v[l].x, re);
+                re = fma(-mi, v[l].y, re);
+                im = fma(mr, v[l].y, im);
+                im = fma(mi, v[l].x, im);
+            }
+            p[off.o[j]] = C2{re, im};
+        }
+    }
+}
+
+// Dense sweep for groups too wide to keep in one thread's registers: the
+// 2^K outputs of a group are split over D/OUTS lanes of the same wave. Every
+// lane reads the whole group (cache hits after the first lane) and the
+// matrix rows it owns; a wave retires all of its loads before any store, so
+// the in-place update is race free.
+template <typename R, int K, int OUTS, typename IT>
+__global__ __launch_bounds__(kBlock) void k_dense_split(typename V2<R>::T *__restrict__ psi,
+                                                        const R *__restrict__ mat, IT n_groups,
+                                                        FixArgs fx, OffArgs<(1 << K)> off)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K;
+    constexpr int LPG = D / OUTS;
+    static_assert(LPG <= 64 && (64 % LPG) == 0, "group must stay inside one wave");
+    const IT total = n_groups * LPG;
+    const IT stride = IT(gridDim.x) * kBlock;
+    for (IT t = IT(blockIdx.x) * kBlock + threadIdx.x; t < total; t += stride) {
+        const IT g = t / LPG;
+        const int r = int(t % LPG);
+        C2 *p = psi + expand<IT>(g, fx);
+        R acc[OUTS][2];
+#pragma unroll
+        for (int o = 0; o < OUTS; ++o) acc[o][0] = acc[o][1] = R(0);
+        for (int l = 0; l < D; ++l) {
+            const C2 x = p[off.o[l]];
+#pragma unroll
+            for (int o = 0; o < OUTS; ++o) {
+                const int j = r * OUTS + o;
+                const R mr = mat[2 * (j * D + l)];
+                const R mi = mat[2 * (j * D + l) + 1];
+                acc[o][0] = fma(mr, x.x, fma(-mi, x.y, acc[o][0]));
+                acc[o][1] = fma(mr, x.y, fma(mi, x.x, acc[o][1]));
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < OUTS; ++o) p[off.o[r * OUTS + o]] = C2{acc[o][0], acc[o][1]};
+    }
+}
+
+// Multiply the amplitudes whose fixed bits match the pinned pattern by one
+// phase (a conditional phase shift, Sec. III-B: with both bits pinned only
+// a quarter of the vector is read and written).
+template <typename R, typename IT>
+__global__ __launch_bounds__(kBlock) void k_phase1(typename V2<R>::T *__restrict__ psi, IT n_items,
+                                                   FixArgs fx, R pr, R pi)
+{
+    using C2 = typename V2<R>::T;
+    const IT stride = IT(gridDim.x) * kBlock;
+    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_items; g += stride) {
+        C2 *p = psi + expand<IT>(g, fx);
+        const C2 a = *p;
+        *p = C2{pr * a.x - pi * a.y, pr * a.y + pi * a.x};
+    }
+}
+
+// Diagonal gate: one elementwise pass; the entry is picked by the target
+// bits of the index. Controls are pinned as fixed bits.
+template <typename R, int K, typename IT>
+__global__ __launch_bounds__(kBlock) void k_diag(typename V2<R>::T *__restrict__ psi,
+                                                 const R *__restrict__ mat, int row_stride,
+                                                 IT n_items, FixArgs fx, OffArgs<K> tg)
+{
+    using C2 = typename V2<R>::T;
+    __shared__ R dsh[2 << K];
+    for (int j = threadIdx.x; j < (1 << K); j += kBlock) {
+        dsh[2 * j] = mat[2 * (size_t(j) * row_stride + j)];
+        dsh[2 * j + 1] = mat[2 * (size_t(j) * row_stride + j) + 1];
+    }
+    __syncthreads();
+    const IT stride = IT(gridDim.x) * kBlock;
+    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_items; g += stride) {
+        const IT i = expand<IT>(g, fx);
+        int j = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) j |= int((i >> tg.o[m]) & 1) << m;
+        const R dr = dsh[2 * j], di = dsh[2 * j + 1];
+        const C2 a = psi[i];
+        psi[i] = C2{dr * a.x - di * a.y, dr * a.y + di * a.x};
+    }
+}
+
+// Monomial gate (one nonzero per row and column): out[dst[j]] = c_j in[j].
+// Only moved or rescaled entries are touched; entries equal to exactly one
+// are moved without arithmetic, so permutation gates are bit-exact.
+template <typename R, int K>
+struct MonoArgs {
+    uint64_t touched;       // bit j: local index j is read and written
+    uint64_t unit;          // bit j: c_j == 1 exactly
+    uint8_t dst[1 << K];
+    R coef[2 << K];
+};
+
+template <typename R, int K, typename IT>
+__global__ __launch_bounds__(kBlock) void k_monomial(typename V2<R>::T *__restrict__ psi,
+                                                     IT n_groups, FixArgs fx,
+                                                     OffArgs<(1 << K)> off, MonoArgs<R, K> ma)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K;
+    const IT stride = IT(gridDim.x) * kBlock;
+    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_groups; g += stride) {
+        C2 *p = psi + expand<IT>(g, fx);
+        C2 v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if ((ma.touched >> j) & 1) v[j] = p[off.o[j]];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (!((ma.touched >> j) & 1)) continue;
+            C2 x = v[j];
+            if (!((ma.unit >> j) & 1)) {
+                const R cr = ma.coef[2 * j], ci = ma.coef[2 * j + 1];
+                x = C2{cr * v[j].x - ci * v[j].y, cr * v[j].y + ci * v[j].x};
+            }
+            p[off.o[ma.dst[j]]] = x;
+        }
+    }
+}
+
+__global__ void k_cast(const double *__restrict__ src, float *__restrict__ dst, size_t count)
+{
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < count;
+         i += size_t(gridDim.x) * kBlock)
+        dst[i] = float(src[i]);
+}
+
+template <typename R>
+__global__ void k_fill_basis(typename V2<R>::T *__restrict__ psi, uint64_t dim, uint64_t index)
+{
+    using C2 = typename V2<R>::T;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < dim;
+         i += uint64_t(gridDim.x) * kBlock)
+        psi[i] = C2{R(i == index ? 1 : 0), R(0)};
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+unsigned grid_for(uint64_t items)
+{
+    uint64_t b = (items + kBlock - 1) / kBlock;
+    const uint64_t cap = 1ull << 22;  // grid-stride beyond 2^30 threads
+    if (b > cap) b = cap;
+    if (b == 0) b = 1;
+    return unsigned(b);
+}
+
+int make_fix(const int *pos, int npos, uint64_t vals, FixArgs &f)
+{
+    if (npos > kMaxFix) return fail(QS_EUNSUPPORTED, "more than %d fixed qubits", kMaxFix);
+    f.nfix = npos;
+    int tmp[64];
+    std::copy(pos, pos + npos, tmp);
+    std::sort(tmp, tmp + npos);
+    for (int i = 0; i < npos; ++i) f.pos[i] = tmp[i];
+    f.vals = vals;
+    return QS_OK;
+}
+
+int fixed_positions(const GateDesc &d, bool with_targets, int *out)
+{
+    int c = 0;
+    if (with_targets)
+        for (int m = 0; m < d.k; ++m) out[c++] = d.targets[m];
+    for (int q = 0; q < 64; ++q)
+        if ((d.ctrl_mask >> q) & 1) out[c++] = q;
+    return c;
+}
+
+template <int D>
+void make_off(const GateDesc &d, OffArgs<D> &o)
+{
+    for (int j = 0; j < D; ++j) {
+        uint64_t v = 0;
+        for (int m = 0; m < d.k; ++m)
+            if ((j >> m) & 1) v |= 1ull << d.targets[m];
+        o.o[j] = v;
+    }
+}
+
+template <typename R, typename IT, int K>
+int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K;
+    FixArgs fx;
+    int pos[64];
+    int np = fixed_positions(d, true, pos);
+    if (int rc = make_fix(pos, np, d.ctrl_vals, fx)) return rc;
+    OffArgs<D> off;
+    make_off<D>(d, off);
+    const IT n_groups = IT(h->dim() >> np);
+    C2 *psi = static_cast<C2 *>(h->psi);
+    const R *m = static_cast<const R *>(dmat);
+    constexpr bool split = (sizeof(R) == 8 && K >= 6);
+    if constexpr (split) {
+        hipLaunchKernelGGL((k_dense_split<R, K, 8, IT>), dim3(grid_for(uint64_t(n_groups) * (D / 8))),
+                           dim3(kBlock), 0, h->stream, psi, m, n_groups, fx, off);
+    } else {
+        hipLaunchKernelGGL((k_dense<R, K, IT>), dim3(grid_for(n_groups)), dim3(kBlock), 0,
+                           h->stream, psi, m, n_groups, fx, off);
+    }
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+template <typename R, typename IT>
+int dense_dispatch(qs_state *h, const GateDesc &d, const void *dmat)
+{
+    switch (d.k) {
+    case 1: return dense_k<R, IT, 1>(h, d, dmat);
+    case 2: return dense_k<R, IT, 2>(h, d, dmat);
+    case 3: return dense_k<R, IT, 3>(h, d, dmat);
+    case 4: return dense_k<R, IT, 4>(h, d, dmat);
+    case 5: return dense_k<R, IT, 5>(h, d, dmat);
+    case 6: return dense_k<R, IT, 6>(h, d, dmat);
+    default: return fail(QS_EUNSUPPORTED, "dense gate width %d", d.k);
+    }
+}
+
+template <typename R, typename IT, int K>
+int diag_k(qs_state *h, const GateDesc &d, const void *dmat, int row_stride)
+{
+    using C2 = typename V2<R>::T;
+    FixArgs fx;
+    int pos[64];
+    int np = fixed_positions(d, false, pos);
+    if (int rc = make_fix(pos, np, d.ctrl_vals, fx)) return rc;
+    OffArgs<K> tg;
+    for (int m = 0; m < K; ++m) tg.o[m] = uint64_t(d.targets[m]);
+    const IT n_items = IT(h->dim() >> np);
+    hipLaunchKernelGGL((k_diag<R, K, IT>), dim3(grid_for(n_items)), dim3(kBlock), 0, h->stream,
+                       static_cast<C2 *>(h->psi), static_cast<const R *>(dmat), row_stride,
+                       n_items, fx, tg);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+template <typename R, typename IT>
+int diag_dispatch(qs_state *h, const GateDesc &d, const void *dmat, int row_stride)
+{
+    switch (d.k) {
+    case 1: return diag_k<R, IT, 1>(h, d, dmat, row_stride);
+    case 2: return diag_k<R, IT, 2>(h, d, dmat, row_stride);
+    case 3: return diag_k<R, IT, 3>(h, d, dmat, row_stride);
+    case 4: return diag_k<R, IT, 4>(h, d, dmat, row_stride);
+    case 5: return diag_k<R, IT, 5>(h, d, dmat, row_stride);
+    case 6: return diag_k<R, IT, 6>(h, d, dmat, row_stride);
+    default: return fail(QS_EUNSUPPORTED, "diagonal gate width %d", d.k);
+    }
+}
+
+template <typename R, typename IT, int K>
+int mono_k(qs_state *h, const GateDesc &d, const double *hmat)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K;
+    FixArgs fx;
+    int pos[64];
+    int np = fixed_positions(d, true, pos);
+    if (int rc = make_fix(pos, np, d.ctrl_vals, fx)) return rc;
+    OffArgs<D> off;
+    make_off<D>(d, off);
+    MonoArgs<R, K> ma;
+    std::memset(&ma, 0, sizeof ma);
+    for (int j = 0; j < D; ++j) {
+        const int dj = d.perm_dst[j];
+        const double cr = hmat[2 * (size_t(dj) * D + j)], ci = hmat[2 * (size_t(dj) * D + j) + 1];
+        ma.dst[j] = uint8_t(dj);
+        ma.coef[2 * j] = R(cr);
+        ma.coef[2 * j + 1] = R(ci);
+        const bool unit = (cr == 1.0 && ci == 0.0);
+        if (unit) ma.unit |= 1ull << j;
+        if (!unit || dj != j) ma.touched |= 1ull << j;
+    }
+    const IT n_groups = IT(h->dim() >> np);
+    hipLaunchKernelGGL((k_monomial<R, K, IT>), dim3(grid_for(n_groups)), dim3(kBlock), 0, h->stream,
+                       static_cast<C2 *>(h->psi), n_groups, fx, off, ma);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+template <typename R, typename IT>
+int mono_dispatch(qs_state *h, const GateDesc &d, const double *hmat)
+{
+    switch (d.k) {
+    case 1: return mono_k<R, IT, 1>(h, d, hmat);
+    case 2: return mono_k<R, IT, 2>(h, d, hmat);
+    case 3: return mono_k<R, IT, 3>(h, d, hmat);
+    case 4: return mono_k<R, IT, 4>(h, d, hmat);
+    case 5: return mono_k<R, IT, 5>(h, d, hmat);
+    case 6: return mono_k<R, IT, 6>(h, d, hmat);
+    default: return fail(QS_EUNSUPPORTED, "monomial gate width %d", d.k);
+    }
+}
+
+template <typename R, typename IT>
+int phase1_t(qs_state *h, const GateDesc &d, double pr, double pi)
+{
+    using C2 = typename V2<R>::T;
+    FixArgs fx;
+    int pos[64];
+    int np = fixed_positions(d, true, pos);
+    uint64_t vals = d.ctrl_vals;
+    for (int m = 0; m < d.k; ++m)
+        if ((d.phase_index >> m) & 1) vals |= 1ull << d.targets[m];
+    if (int rc = make_fix(pos, np, vals, fx)) return rc;
+    const IT n_items = IT(h->dim() >> np);
+    hipLaunchKernelGGL((k_phase1<R, IT>), dim3(grid_for(n_items)), dim3(kBlock), 0, h->stream,
+                       static_cast<C2 *>(h->psi), n_items, fx, R(pr), R(pi));
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Exact structure classification (no tolerance: a structured gate must be
+// structured bit for bit, otherwise the dense sweep is used).
+// ---------------------------------------------------------------------------
+void classify(const double *m, int k, GateDesc &d)
+{
+    const int D = 1 << k;
+    auto re = [&](int r, int c) { return m[2 * (size_t(r) * D + c)]; };
+    auto im = [&](int r, int c) { return m[2 * (size_t(r) * D + c) + 1]; };
+    auto nz = [&](int r, int c) { return re(r, c) != 0.0 || im(r, c) != 0.0; };
+    bool diag = true;
+    for (int r = 0; r < D && diag; ++r)
+        for (int c = 0; c < D; ++c)
+            if (r != c && nz(r, c)) { diag = false; break; }
+    if (diag) {
+        int nonunit = 0, idx = 0;
+        for (int j = 0; j < D; ++j)
+            if (!(re(j, j) == 1.0 && im(j, j) == 0.0)) { ++nonunit; idx = j; }
+        if (nonunit == 0) { d.cls = GC_IDENTITY; return; }
+        if (nonunit == 1) { d.cls = GC_PHASE1; d.phase_index = idx; return; }
+        d.cls = GC_DIAG;
+        return;
+    }
+    // monomial: exactly one nonzero in every column and every row
+    std::vector<int> row_used(D, 0);
+    for (int c = 0; c < D; ++c) {
+        int cnt = 0, rr = -1;
+        for (int r = 0; r < D; ++r)
+            if (nz(r, c)) { ++cnt; rr = r; }
+        if (cnt != 1 || row_used[rr]) { d.cls = GC_DENSE; return; }
+        row_used[rr] = 1;
+        d.perm_dst[c] = rr;
+    }
+    d.cls = GC_MONOMIAL;
+}
+
+int launch_dense(qs_state *h, const GateDesc &d, const void *dmat)
+{
+    const bool small = h->n <= 31;
+    if (h->dtype == QS_C128)
+        return small ? dense_dispatch<double, uint32_t>(h, d, dmat)
+                     : dense_dispatch<double, uint64_t>(h, d, dmat);
+    return small ? dense_dispatch<float, uint32_t>(h, d, dmat)
+                 : dense_dispatch<float, uint64_t>(h, d, dmat);
+}
+
+int launch_diag(qs_state *h, const GateDesc &d, const void *dmat, int row_stride)
+{
+    const bool small = h->n <= 31;
+    if (h->dtype == QS_C128)
+        return small ? diag_dispatch<double, uint32_t>(h, d, dmat, row_stride)
+                     : diag_dispatch<double, uint64_t>(h, d, dmat, row_stride);
+    return small ? diag_dispatch<float, uint32_t>(h, d, dmat, row_stride)
+                 : diag_dispatch<float, uint64_t>(h, d, dmat, row_stride);
+}
+
+int launch_monomial_host(qs_state *h, const GateDesc &d, const double *hmat)
+{
+    const bool small = h->n <= 31;
+    if (h->dtype == QS_C128)
+        return small ? mono_dispatch<double, uint32_t>(h, d, hmat)
+                     : mono_dispatch<double, uint64_t>(h, d, hmat);
+    return small ? mono_dispatch<float, uint32_t>(h, d, hmat)
+                 : mono_dispatch<float, uint64_t>(h, d, hmat);
+}
+
+int launch_phase1_host(qs_state *h, const GateDesc &d, double pr, double pi)
+{
+    const bool small = h->n <= 31;
+    if (h->dtype == QS_C128)
+        return small ? phase1_t<double, uint32_t>(h, d, pr, pi) : phase1_t<double, uint64_t>(h, d, pr, pi);
+    return small ? phase1_t<float, uint32_t>(h, d, pr, pi) : phase1_t<float, uint64_t>(h, d, pr, pi);
+}
+
+int launch_cast_f64_to_f32(hipStream_t s, const double *src, float *dst, size_t count)
+{
+    hipLaunchKernelGGL(k_cast, dim3(grid_for(count)), dim3(kBlock), 0, s, src, dst, count);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+int launch_set_basis(qs_state *h, uint64_t index)
+{
+    if (h->dtype == QS_C128)
+        hipLaunchKernelGGL(k_fill_basis<double>, dim3(grid_for(h->dim())), dim3(kBlock), 0,
+                           h->stream, static_cast<double2 *>(h->psi), h->dim(), index);
+    else
+        hipLaunchKernelGGL(k_fill_basis<float>, dim3(grid_for(h->dim())), dim3(kBlock), 0,
+                           h->stream, static_cast<float2 *>(h->psi), h->dim(), index);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+// One gate with its FP64 matrix on the host: classify, stage what the
+// chosen kernel reads, launch.
+int enqueue_gate(qs_state *h, const GateDesc &din, const double *hmat)
+{
+    GateDesc d = din;
+    classify(hmat, d.k, d);
+    const size_t D = size_t(1) << d.k;
+    switch (d.cls) {
+    case GC_IDENTITY:
+        return QS_OK;
+    case GC_PHASE1: {
+        const size_t j = size_t(d.phase_index);
+        return launch_phase1_host(h, d, hmat[2 * (j * D + j)], hmat[2 * (j * D + j) + 1]);
+    }
+    case GC_MONOMIAL:
+        return launch_monomial_host(h, d, hmat);
+    default:
+        break;
+    }
+    // dense and diagonal kernels read the matrix from device memory
+    const size_t count = 2 * D * D;
+    void *dm = nullptr;
+    if (int rc = h->stage.put(h->stream, hmat, count * sizeof(double), &dm)) return rc;
+    if (h->dtype == QS_C64) {
+        void *d32 = nullptr;
+        if (int rc = h->stage.reserve(h->stream, count * sizeof(float), &d32)) return rc;
+        if (int rc = launch_cast_f64_to_f32(h->stream, static_cast<double *>(dm),
+                                            static_cast<float *>(d32), count))
+            return rc;
+        dm = d32;
+    }
+    if (d.cls == GC_DIAG) return launch_diag(h, d, dm, int(D));
+    return launch_dense(h, d, dm);
+}
+
+}  // namespace qs
