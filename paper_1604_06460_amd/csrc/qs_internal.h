@@ -128,6 +128,7 @@ int plan_fusion(int n_qubits, int n_gates, const int *k, const int *targets,
 int reduce_norm2(qs_state *h, double *out);
 int reduce_pauli(qs_state *h, uint64_t xm, uint64_t ym, uint64_t zm, double *re, double *im);
 int gather_amplitudes(qs_state *h, int count, const uint64_t *indices, void *host_dst);
+int emulate_qft(qs_state *h, int q_lo, int m, int inverse);
 int measure(qs_state *h, int m, const int *qubits, int shots, const double *u,
             uint64_t *outcomes, double *probs, int collapse);
 
