@@ -109,6 +109,11 @@ int qs_set_zero(qs_handle h);
 int qs_get_state(qs_handle h, void *host_dst);
 int qs_set_state(qs_handle h, const void *host_src);
 
+/* Copy 2^n amplitudes of the handle's dtype from device memory (e.g. a
+ * resident input state) into the state, enqueued on the handle's stream.
+ * The source must not overlap the state. */
+int qs_load_device(qs_handle h, const void *device_src);
+
 /* Copy the amplitudes at `count` indices (each < 2^n) to host_dst (count
  * amplitudes of the handle's dtype). For spot checks of large states
  * without a full copy. Waits for the stream. */

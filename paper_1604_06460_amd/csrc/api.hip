@@ -296,6 +296,18 @@ int qs_set_state(qs_handle h, const void *host_src)
     return QS_OK;
 }
 
+int qs_load_device(qs_handle h, const void *device_src)
+{
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!device_src) return fail(QS_EINVAL, "NULL device source");
+    const size_t bytes = h->dim() * h->amp_bytes();
+    const char *s = static_cast<const char *>(device_src), *d = static_cast<const char *>(h->psi);
+    if (s < d + bytes && d < s + bytes) return fail(QS_EINVAL, "source overlaps the state");
+    QS_HIP(hipMemcpyAsync(h->psi, device_src, bytes, hipMemcpyDeviceToDevice, h->stream));
+    return QS_OK;
+}
+
 int qs_get_amplitudes(qs_handle h, int count, const uint64_t *indices, void *host_dst)
 {
     clear_error();

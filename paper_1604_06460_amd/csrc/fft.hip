@@ -22,23 +22,27 @@
 // row XOR-swizzled by the next 4, which keeps both the strided and the
 // contiguous stage accesses free of bank conflicts.
 //
-// Twiddles: exact integer exponents (k * l reduced mod 2^bits) are turned
-// into angles and evaluated with sincospi in FP64; stage twiddles come from
-// a 2^10-entry table built the same way. FP32 states use the FP64 twiddles
-// rounded to FP32.
+// Twiddles are products of two table entries held in LDS. Stage twiddles:
+// exp(s 2 pi i y / 1024) = A[y mod 32] * B[y / 32]. Pass twiddles: per
+// column, exp(s 2 pi i k_rest l / N_j) = GA[l mod 32] * GB[l / 32] with the
+// exponents k_rest * l reduced exactly in integers before the angle is
+// formed. Every table entry is one FP64 sincospi call; FP32 states round
+// the FP64 values.
 #include "qs_internal.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace qs {
 namespace {
 
-constexpr int kThreads = 256;
+template <typename R> struct FftThreads { static constexpr int value = 256; };
+template <> struct FftThreads<float> { static constexpr int value = 512; };
 constexpr int kRmax = 10;           // digit width limit (bits)
-constexpr int kTab = 1 << kRmax;    // stage-twiddle table size
 constexpr size_t kLdsBytes = 64 * 1024;
+constexpr int kMaxCols = 16;
 
 template <typename R> struct V2;
 template <> struct V2<double> { using T = double2; };
@@ -54,12 +58,12 @@ struct PassArgs {
     int r;              // digit width
     int dig_lo;         // absolute position of the digit
     int cb;             // number of column bits
-    int col_pos[6];     // absolute source positions of the column bits (ascending)
+    int col_pos[6];     // absolute source positions of the column bits
     int nrest;
     int rest_pos[40];   // remaining bits (ascending), enumerated by workgroup
     int nst;            // in-LDS stages
     int rho[4], sigma[4];
-    // global twiddle after this pass (tw_bits == 0: none)
+    // pass twiddle (tw_bits == 0: none)
     int tw_bits;        // log2 N_j
     int krest_lo, krest_bits;
     int sgn;            // +1 forward QFT, -1 inverse
@@ -68,7 +72,7 @@ struct PassArgs {
     int final_pass;
     int q_lo, m;
     int ndig;
-    int dpos[4], dw[4], doff[4];   // absolute position, width, output offset of each digit
+    int dpos[8], dw[8], doff[8];   // absolute position, width, output offset of each digit
 };
 
 __device__ __forceinline__ int phys(int c, int p, int L)
@@ -76,11 +80,27 @@ __device__ __forceinline__ int phys(int c, int p, int L)
     return c * (L + 4) + (p ^ ((p >> 4) & 15));
 }
 
-// Natural-order DFT of RAD register values (radix-2 decimation in
-// frequency followed by a compile-time bit reversal of the register names).
-// tab[y * tstride] = exp(s 2 pi i y / RAD).
+// exp(s 2 pi i num / 2^bits) with num already reduced below 2^bits.
+template <typename C2, typename R>
+__device__ __forceinline__ C2 unit_root(uint64_t num, int bits, int sgn)
+{
+    double sn, cs;
+    sincospi(double(sgn) * 2.0 * (double(num) / double(1ull << bits)), &sn, &cs);
+    return C2{R(cs), R(sn)};
+}
+
+// Stage twiddle exp(s 2 pi i y / 1024) from the two 32-entry tables.
+template <typename C2>
+__device__ __forceinline__ C2 stw(const C2 *__restrict__ ta, const C2 *__restrict__ tb, int y)
+{
+    return (y & 31) ? ((y >> 5) ? cmul(ta[y & 31], tb[y >> 5]) : ta[y & 31]) : tb[y >> 5];
+}
+
+// Natural-order DFT of RAD register values (radix-2 decimation in frequency
+// followed by a compile-time bit reversal of the register names).
 template <typename C2, int RAD>
-__device__ __forceinline__ void dft_reg(C2 (&v)[RAD], const C2 *__restrict__ tab, int tstride)
+__device__ __forceinline__ void dft_reg(C2 (&v)[RAD], const C2 *__restrict__ ta,
+                                        const C2 *__restrict__ tb)
 {
 #pragma unroll
     for (int h = RAD / 2; h >= 1; h >>= 1) {
@@ -91,7 +111,8 @@ __device__ __forceinline__ void dft_reg(C2 (&v)[RAD], const C2 *__restrict__ tab
                 const C2 a = v[b + j], c = v[b + j + h];
                 v[b + j] = C2{a.x + c.x, a.y + c.y};
                 const C2 d{a.x - c.x, a.y - c.y};
-                v[b + j + h] = (j == 0) ? d : cmul(d, tab[j * (RAD / (2 * h)) * tstride]);
+                // exp(s 2 pi i j / (2h)) = 1024-table entry j * 512 / h
+                v[b + j + h] = (j == 0) ? d : cmul(d, tb[(j * (512 / h)) >> 5]);
             }
         }
     }
@@ -109,13 +130,13 @@ __device__ __forceinline__ void dft_reg(C2 (&v)[RAD], const C2 *__restrict__ tab
 
 // One radix-RAD stage over the tile in LDS: digit at sigma (within r bits),
 // then the twiddle exp(s 2 pi i k' l / 2^(sigma+rho)) with k' = bits below.
-template <typename C2, int RHO>
-__device__ void lds_stage(C2 *lds, int r, int C, int sigma, const C2 *__restrict__ tab)
+template <typename C2, int RHO, int kThreads>
+__device__ void lds_stage(C2 *lds, int r, int C, int sigma, const C2 *__restrict__ ta,
+                          const C2 *__restrict__ tb)
 {
     constexpr int RAD = 1 << RHO;
     const int L = 1 << r;
     const int items = C << (r - RHO);
-    const int tstride_dft = kTab >> RHO;
     const int tw_shift = kRmax - (sigma + RHO);
     for (int it = threadIdx.x; it < items; it += kThreads) {
         const int c = it % C;
@@ -125,12 +146,12 @@ __device__ void lds_stage(C2 *lds, int r, int C, int sigma, const C2 *__restrict
         C2 v[RAD];
 #pragma unroll
         for (int d = 0; d < RAD; ++d) v[d] = lds[phys(c, hi | (d << sigma) | lo, L)];
-        dft_reg<C2, RAD>(v, tab, tstride_dft);
+        dft_reg<C2, RAD>(v, ta, tb);
         if (sigma > 0) {
 #pragma unroll
             for (int l = 1; l < RAD; ++l) {
-                const int y = ((lo * l) << tw_shift) & (kTab - 1);
-                v[l] = cmul(v[l], tab[y]);
+                const int y = ((lo * l) << tw_shift) & 1023;
+                v[l] = cmul(v[l], stw(ta, tb, y));
             }
         }
 #pragma unroll
@@ -138,20 +159,22 @@ __device__ void lds_stage(C2 *lds, int r, int C, int sigma, const C2 *__restrict
     }
 }
 
-template <typename R>
+template <typename R, int kThreads = FftThreads<R>::value>
 __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename V2<R>::T *__restrict__ src,
                                                        typename V2<R>::T *__restrict__ dst,
-                                                       PassArgs pa,
-                                                       const typename V2<R>::T *__restrict__ tab)
+                                                       PassArgs pa)
 {
     using C2 = typename V2<R>::T;
     extern __shared__ unsigned char lds_raw[];
-    C2 *lds = reinterpret_cast<C2 *>(lds_raw);
     const int r = pa.r, L = 1 << r, C = 1 << pa.cb;
-    // tile base: workgroup index deposited into the remaining bit positions
+    C2 *lds = reinterpret_cast<C2 *>(lds_raw);
+    C2 *ta = lds + size_t(C) * (L + 4);   // exp(s 2 pi i j / 1024), j < 32
+    C2 *tb = ta + 32;                      // exp(s 2 pi i 32 j / 1024), j < 32
+    C2 *ga = tb + 32;                      // [C][32] pass twiddle, low 5 bits of l
+    C2 *gb = ga + 32 * C;                  // [C][32] pass twiddle, high bits of l
     uint64_t base = 0;
     {
-        uint64_t w = blockIdx.x;
+        const uint64_t w = blockIdx.x;
         for (int i = 0; i < pa.nrest; ++i) base |= ((w >> i) & 1ull) << pa.rest_pos[i];
     }
     auto colbits = [&](int c) {
@@ -164,17 +187,32 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename V2<R>::T *
         const int c = e & (C - 1), p = e >> pa.cb;
         lds[phys(c, p, L)] = src[base | (uint64_t(p) << pa.dig_lo) | colbits(c)];
     }
+    // twiddle tables (overlap the loads in flight)
+    for (int t = threadIdx.x; t < 64 + (pa.tw_bits ? 64 * C : 0); t += kThreads) {
+        if (t < 32) {
+            ta[t] = unit_root<C2, R>(uint64_t(t), kRmax, pa.sgn);
+        } else if (t < 64) {
+            tb[t - 32] = unit_root<C2, R>(uint64_t(t - 32) << 5, kRmax, pa.sgn);
+        } else {
+            const int u = t - 64, c = u >> 6, j = u & 31, hi = (u >> 5) & 1;
+            const uint64_t kr = ((base | colbits(c)) >> pa.krest_lo) & ((1ull << pa.krest_bits) - 1);
+            const uint64_t mask = (1ull << pa.tw_bits) - 1;
+            const uint64_t e2 = (kr * (uint64_t(j) << (hi ? 5 : 0))) & mask;
+            (hi ? gb : ga)[c * 32 + j] = unit_root<C2, R>(e2, pa.tw_bits, pa.sgn);
+        }
+    }
     __syncthreads();
     for (int s = 0; s < pa.nst; ++s) {
         switch (pa.rho[s]) {
-        case 1: lds_stage<C2, 1>(lds, r, C, pa.sigma[s], tab); break;
-        case 2: lds_stage<C2, 2>(lds, r, C, pa.sigma[s], tab); break;
-        case 3: lds_stage<C2, 3>(lds, r, C, pa.sigma[s], tab); break;
-        default: lds_stage<C2, 4>(lds, r, C, pa.sigma[s], tab); break;
+        case 1: lds_stage<C2, 1, kThreads>(lds, r, C, pa.sigma[s], ta, tb); break;
+        case 2: lds_stage<C2, 2, kThreads>(lds, r, C, pa.sigma[s], ta, tb); break;
+        case 3: lds_stage<C2, 3, kThreads>(lds, r, C, pa.sigma[s], ta, tb); break;
+        default: lds_stage<C2, 4, kThreads>(lds, r, C, pa.sigma[s], ta, tb); break;
         }
         __syncthreads();
     }
     // store: output digit l sits at the position its stages wrote it to
+    const uint64_t fmask = ((1ull << pa.m) - 1) << pa.q_lo;
     for (int e = threadIdx.x; e < (L << pa.cb); e += kThreads) {
         const int c = e & (C - 1), l = e >> pa.cb;
         int p = 0, sh = 0;
@@ -183,39 +221,21 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename V2<R>::T *
             sh += pa.rho[s];
         }
         C2 v = lds[phys(c, p, L)];
-        const uint64_t sidx = base | (uint64_t(l) << pa.dig_lo) | colbits(c);
         if (pa.tw_bits) {
-            const uint64_t kr = (sidx >> pa.krest_lo) & ((1ull << pa.krest_bits) - 1);
-            const uint64_t e2 = (kr * uint64_t(l)) & ((1ull << pa.tw_bits) - 1);
-            double sn, cs;
-            sincospi(double(pa.sgn) * 2.0 * (double(e2) / double(1ull << pa.tw_bits)), &sn, &cs);
-            const double vr = double(v.x), vi = double(v.y);
-            v = C2{R(vr * cs - vi * sn), R(vr * sn + vi * cs)};
+            const C2 w = (l >> 5) ? cmul(ga[c * 32 + (l & 31)], gb[c * 32 + (l >> 5)]) : ga[c * 32 + l];
+            v = cmul(v, w);
         }
         if (pa.scale != 1.0) v = C2{R(double(v.x) * pa.scale), R(double(v.y) * pa.scale)};
+        const uint64_t sidx = base | (uint64_t(l) << pa.dig_lo) | colbits(c);
         uint64_t didx = sidx;
         if (pa.final_pass) {
-            const uint64_t fmask = ((1ull << pa.m) - 1) << pa.q_lo;
             uint64_t f = 0;
-            for (int d = 0; d < pa.ndig; ++d) {
-                const uint64_t val = (sidx >> pa.dpos[d]) & ((1ull << pa.dw[d]) - 1);
-                f |= val << pa.doff[d];
-            }
+            for (int d = 0; d < pa.ndig; ++d)
+                f |= ((sidx >> pa.dpos[d]) & ((1ull << pa.dw[d]) - 1)) << pa.doff[d];
             didx = (sidx & ~fmask) | (f << pa.q_lo);
         }
         dst[didx] = v;
     }
-}
-
-template <typename R>
-__global__ void k_twiddle_table(typename V2<R>::T *__restrict__ tab, int sgn)
-{
-    using C2 = typename V2<R>::T;
-    const int y = blockIdx.x * kThreads + threadIdx.x;
-    if (y >= kTab) return;
-    double sn, cs;
-    sincospi(double(sgn) * 2.0 * double(y) / double(kTab), &sn, &cs);
-    tab[y] = C2{R(cs), R(sn)};
 }
 
 void stage_plan(int r, PassArgs &pa)
@@ -232,13 +252,33 @@ void stage_plan(int r, PassArgs &pa)
     }
 }
 
+// Pass shape: widest digit and LDS bytes per workgroup tile. Narrower digits
+// mean more passes but longer contiguous runs per global access (the tile
+// holds LDS/(2^r * amplitude) columns). Overridable for tuning through
+// QS_FFT_DIGIT / QS_FFT_LDS_KB.
+struct FftShape {
+    int digit = 10;
+    size_t lds = kLdsBytes;
+};
+
+FftShape fft_shape()
+{
+    FftShape s;
+    if (const char *e = getenv("QS_FFT_DIGIT")) s.digit = std::max(1, std::min(kRmax, atoi(e)));
+    if (const char *e = getenv("QS_FFT_LDS_KB"))
+        s.lds = size_t(std::max(4, std::min(64, atoi(e)))) * 1024;
+    return s;
+}
+
 template <typename R>
 int run_fft(qs_state *h, int q_lo, int m, int inverse)
 {
     using C2 = typename V2<R>::T;
     const int n = h->n;
-    const int P = (m + kRmax - 1) / kRmax;
-    int width[4], pos[4];  // digit j from the top of the field
+    const FftShape shape = fft_shape();
+    const int P = (m + shape.digit - 1) / shape.digit;
+    if (P > 8) return fail(QS_EUNSUPPORTED, "QFT field needs more than 8 passes");
+    int width[8], pos[8];  // digit j from the top of the field
     {
         int rem = m;
         for (int j = 0; j < P; ++j) {
@@ -252,11 +292,6 @@ int run_fft(qs_state *h, int q_lo, int m, int inverse)
         }
     }
     const int sgn = inverse ? -1 : 1;
-    void *dtab = nullptr;
-    if (int rc = h->stage.reserve(h->stream, sizeof(C2) * kTab, &dtab)) return rc;
-    hipLaunchKernelGGL(k_twiddle_table<R>, dim3(kTab / kThreads), dim3(kThreads), 0, h->stream,
-                       static_cast<C2 *>(dtab), sgn);
-    QS_HIP(hipGetLastError());
     if (P > 1)
         if (int rc = ensure_scratch(h)) return rc;
     for (int j = 0; j < P; ++j) {
@@ -266,13 +301,14 @@ int run_fft(qs_state *h, int q_lo, int m, int inverse)
         pa.dig_lo = pos[j];
         pa.sgn = sgn;
         pa.scale = 1.0;
+        pa.q_lo = q_lo;
+        pa.m = m;
         stage_plan(pa.r, pa);
         const bool last = (j == P - 1);
-        // column bits
         // columns so that the unpadded tile fills the LDS budget
         int maxcb = 0;
-        while ((sizeof(C2) << (pa.r + maxcb + 1)) <= kLdsBytes) ++maxcb;
-        const int want = std::max(0, std::min({maxcb, 6, n - pa.r}));
+        while ((sizeof(C2) << (pa.r + maxcb + 1)) <= shape.lds && (2 << maxcb) <= kMaxCols) ++maxcb;
+        const int want = std::max(0, std::min(maxcb, n - pa.r));
         std::vector<int> cols;
         if (last && P > 1) {
             // destination-contiguous bits: spectators below the field, then the
@@ -301,8 +337,6 @@ int run_fft(qs_state *h, int q_lo, int m, int inverse)
         if (last) pa.scale = 1.0 / std::sqrt(std::ldexp(1.0, m));
         if (last && P > 1) {
             pa.final_pass = 1;
-            pa.q_lo = q_lo;
-            pa.m = m;
             pa.ndig = P;
             int off = 0;
             for (int d = 0; d < P; ++d) {
@@ -313,12 +347,13 @@ int run_fft(qs_state *h, int q_lo, int m, int inverse)
             }
         }
         const uint64_t tiles = h->dim() >> (pa.r + pa.cb);
-        const size_t lds = sizeof(C2) * size_t((1 << pa.r) + 4) << pa.cb;
+        const size_t C = size_t(1) << pa.cb;
+        const size_t lds = sizeof(C2) * (size_t((1 << pa.r) + 4) * C + 64 + 64 * C);
         const C2 *src = static_cast<const C2 *>(h->psi);
         C2 *dst = (last && P > 1) ? static_cast<C2 *>(h->scratch) : static_cast<C2 *>(h->psi);
         if (tiles > 0x7fffffffull) return fail(QS_EUNSUPPORTED, "FFT tile count too large");
-        hipLaunchKernelGGL(k_fft_pass<R>, dim3(unsigned(tiles)), dim3(kThreads), lds, h->stream, src,
-                           dst, pa, static_cast<const C2 *>(dtab));
+        hipLaunchKernelGGL(k_fft_pass<R>, dim3(unsigned(tiles)), dim3(FftThreads<R>::value), lds, h->stream, src,
+                           dst, pa);
         QS_HIP(hipGetLastError());
     }
     if (P > 1) {
@@ -338,10 +373,11 @@ int emulate_qft(qs_state *h, int q_lo, int m, int inverse)
 {
     static bool lds_ok = false;
     if (!lds_ok) {
+        const int cap = int(kLdsBytes + 16 * 1024);
         QS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_pass<double>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsBytes + 4096)));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, cap));
         QS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_pass<float>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsBytes + 4096)));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, cap));
         lds_ok = true;
     }
     return h->dtype == QS_C128 ? run_fft<double>(h, q_lo, m, inverse) : run_fft<float>(h, q_lo, m, inverse);

@@ -15,6 +15,7 @@
 #include "qs_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 namespace qs {
@@ -52,7 +53,46 @@ __device__ __forceinline__ IT expand(IT g, const FixArgs &f)
 // Dense sweep: one thread owns one group, holds its 2^K amplitudes in
 // registers and writes out_j = sum_l M[j][l] in_l. The matrix pointer and
 // every index into it are uniform, so the entries are read through scalar
-// loads and used as SGPR operands of the FMAs.
+// loads and used as SGPR operands of the FMAs. Loops over output rows and
+// over 8-entry chunks of a row are kept rolled, so at most one chunk (16
+// reals) is resident in SGPRs; fully unrolled, the compiler hoists the whole
+// matrix and spills scalar registers into vector lanes.
+template <typename R, typename C2, int D, int L0>
+__device__ __forceinline__ void row_chunk(const R *__restrict__ row, const C2 (&v)[D], R &re, R &im)
+{
+#pragma unroll
+    for (int l = L0; l < L0 + (D < 8 ? D : 8); ++l) {
+        const R mr = row[2 * l];
+        const R mi = row[2 * l + 1];
+        re = fma(mr, v[l].x, re);
+        re = fma(-mi, v[l].y, re);
+        im = fma(mr, v[l].y, im);
+        im = fma(mi, v[l].x, im);
+    }
+}
+
+template <typename R, typename C2, int D>
+__device__ __forceinline__ void row_dot(const R *__restrict__ row, const C2 (&v)[D], R &re, R &im)
+{
+    if constexpr (D <= 8) {
+        row_chunk<R, C2, D, 0>(row, v, re, im);
+    } else {
+#pragma unroll 1
+        for (int c = 0; c < D / 8; ++c) {
+            switch (c) {
+            case 0: row_chunk<R, C2, D, 0>(row, v, re, im); break;
+            case 1: row_chunk<R, C2, D, 8>(row, v, re, im); break;
+            case 2: if constexpr (D > 16) row_chunk<R, C2, D, 16>(row, v, re, im); break;
+            case 3: if constexpr (D > 16) row_chunk<R, C2, D, 24>(row, v, re, im); break;
+            case 4: if constexpr (D > 32) row_chunk<R, C2, D, 32>(row, v, re, im); break;
+            case 5: if constexpr (D > 32) row_chunk<R, C2, D, 40>(row, v, re, im); break;
+            case 6: if constexpr (D > 32) row_chunk<R, C2, D, 48>(row, v, re, im); break;
+            default: if constexpr (D > 32) row_chunk<R, C2, D, 56>(row, v, re, im); break;
+            }
+        }
+    }
+}
+
 template <typename R, int K, typename IT>
 __global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict__ psi,
                                                   const R *__restrict__ mat, IT n_groups,
@@ -66,20 +106,72 @@ __global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict_
         C2 v[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) v[j] = p[off.o[j]];
-#pragma unroll
+#pragma unroll 1
         for (int j = 0; j < D; ++j) {
             R re = R(0), im = R(0);
-#pragma unroll
-            for (int l = 0; l < D; ++l) {
-                const R mr = mat[2 * (j * D + l)];
-                const R mi = mat[2 * (j * D + l) + 1];
-                re = fma(mr, v[l].x, re);
-                re = fma(-mi, v[l].y, re);
-                im = fma(mr, v[l].y, im);
-                im = fma(mi, v[l].x, im);
-            }
+            row_dot<R, C2, D>(mat + 2 * j * D, v, re, im);
             p[off.o[j]] = C2{re, im};
         }
+    }
+}
+
+// Dense sweep for blocks with targets inside a cache line. A wave owns a
+// tile of 2^(6+K) amplitudes spanned by index bits 0..5, the targets above
+// bit 5, and the lowest free bits above bit 5 ("extra" bits), as many as
+// there are targets below bit 6. Loads and stores use the layout lane =
+// bits 0..5, register = the other tile bits, so every wave-wide access is
+// 64 consecutive amplitudes. An LDS transpose regroups the tile so each lane
+// owns one whole group (lane = the free tile bits, register = the local
+// index), the group is multiplied in registers, and the transpose is undone
+// before the store. Positions are compact tile indices; the LDS slot of
+// position p XORs its low bits with the next ones, which spreads both
+// layouts over distinct banks.
+template <int D>
+struct LdsArgs {
+    int lane_pos[6];   // compact position of each lane bit in the compute layout
+    int offc[D];       // compact position offset of local index j
+};
+
+template <typename C2>
+__device__ __forceinline__ int lds_slot(int p)
+{
+    constexpr int SW = 256 / int(sizeof(C2));  // elements per 256-byte bank row
+    return p ^ ((p / SW) & (SW - 1));
+}
+
+template <typename R, int K, typename IT>
+__global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict__ psi,
+                                                  const R *__restrict__ mat, IT n_tiles,
+                                                  FixArgs fx, OffArgs<(1 << K)> offl,
+                                                  LdsArgs<(1 << K)> la)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K;
+    __shared__ C2 tile[64 * D];
+    const int lane = threadIdx.x;
+    int lp = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) lp |= ((lane >> b) & 1) << la.lane_pos[b];
+    for (IT t = IT(blockIdx.x); t < n_tiles; t += IT(gridDim.x)) {
+        C2 *p = psi + expand<IT>(t, fx) + lane;
+        C2 v[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) v[r] = p[offl.o[r]];
+#pragma unroll
+        for (int r = 0; r < D; ++r) tile[lds_slot<C2>(lane + 64 * r)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = tile[lds_slot<C2>(lp | la.offc[j])];
+#pragma unroll 1
+        for (int j = 0; j < D; ++j) {
+            R re = R(0), im = R(0);
+            row_dot<R, C2, D>(mat + 2 * j * D, v, re, im);
+            tile[lds_slot<C2>(lp | la.offc[j])] = C2{re, im};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < D; ++r) p[offl.o[r]] = tile[lds_slot<C2>(lane + 64 * r)];
+        __syncthreads();
     }
 }
 
@@ -277,6 +369,55 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
     const IT n_groups = IT(h->dim() >> np);
     C2 *psi = static_cast<C2 *>(h->psi);
     const R *m = static_cast<const R *>(dmat);
+    // targets inside a 128-byte line: stage the tile through LDS
+    constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
+    constexpr bool lds_capable = (sizeof(R) == 8) ? (K <= 5) : (K <= 6);
+    int mint = 64;
+    for (int i = 0; i < K; ++i) mint = std::min(mint, d.targets[i]);
+    if constexpr (lds_capable) {
+        if (d.ctrl_mask == 0 && mint < kLineBits && h->n >= 6 + K && !getenv("QS_NO_LDS_SWEEP")) {
+            uint64_t tmask = 0;
+            for (int i = 0; i < K; ++i) tmask |= 1ull << d.targets[i];
+            int klo = 0;
+            for (int i = 0; i < K; ++i) klo += d.targets[i] < 6;
+            std::vector<int> extra;
+            for (int b = 6; b < h->n && int(extra.size()) < klo; ++b)
+                if (!((tmask >> b) & 1)) extra.push_back(b);
+            std::vector<int> P = {0, 1, 2, 3, 4, 5};
+            for (int i = 0; i < K; ++i)
+                if (d.targets[i] >= 6) P.push_back(d.targets[i]);
+            for (int b : extra) P.push_back(b);
+            std::sort(P.begin(), P.end());
+            auto compact = [&](int b) { return int(std::lower_bound(P.begin(), P.end(), b) - P.begin()); };
+            OffArgs<D> offl;
+            for (int r = 0; r < D; ++r) {
+                uint64_t o = 0;
+                for (int i = 0; i < K; ++i)
+                    if ((r >> i) & 1) o |= 1ull << P[size_t(6 + i)];
+                offl.o[r] = o;
+            }
+            LdsArgs<D> la;
+            std::vector<int> lane_bits;
+            for (int b = 0; b < 6; ++b)
+                if (!((tmask >> b) & 1)) lane_bits.push_back(b);
+            for (int b : extra) lane_bits.push_back(b);
+            for (int b = 0; b < 6; ++b) la.lane_pos[b] = compact(lane_bits[size_t(b)]);
+            for (int j = 0; j < D; ++j) {
+                int o = 0;
+                for (int i = 0; i < K; ++i)
+                    if ((j >> i) & 1) o |= 1 << compact(d.targets[i]);
+                la.offc[j] = o;
+            }
+            FixArgs ft;
+            if (int rc = make_fix(P.data(), int(P.size()), 0, ft)) return rc;
+            const IT n_tiles = IT(h->dim() >> (6 + K));
+            const uint64_t grid = std::min<uint64_t>(uint64_t(n_tiles), 1ull << 22);
+            hipLaunchKernelGGL((k_dense_lds<R, K, IT>), dim3(unsigned(grid)), dim3(64), 0, h->stream, psi,
+                               m, n_tiles, ft, offl, la);
+            QS_HIP(hipGetLastError());
+            return QS_OK;
+        }
+    }
     constexpr bool split = (sizeof(R) == 8 && K >= 6);
     if constexpr (split) {
         hipLaunchKernelGGL((k_dense_split<R, K, 8, IT>), dim3(grid_for(uint64_t(n_groups) * (D / 8))),

@@ -64,6 +64,7 @@ _sig("qs_get_state", [_P, _P])
 _sig("qs_set_state", [_P, _P])
 _sig("qs_sync", [_P])
 _sig("qs_get_amplitudes", [_P, _I, _P, _P])
+_sig("qs_load_device", [_P, _P])
 _sig("qs_apply_gate", [_P, _I, _P, _P, _U64, _U64])
 _sig("qs_apply_fused", [_P, _I, _P, _P, _P])
 _sig("qs_plan_fusion", [C.POINTER(Circuit), _I, _I, C.POINTER(_I), _P, _P, _P])
@@ -221,6 +222,9 @@ class State:
         if a.size != 1 << self.n:
             raise ValueError("state must have 2^n entries")
         _chk(_L.qs_set_state(self._h, _ptr(a)))
+
+    def load_device(self, device_ptr):
+        _chk(_L.qs_load_device(self._h, device_ptr))
 
     def amplitudes(self, indices):
         idx = np.ascontiguousarray(indices, dtype=np.uint64)
