@@ -44,6 +44,21 @@ def qft_gate_bytes(n, amp):
     return n * 2 * amp * N + n_cr * 2 * amp * N / 4 + (n // 2) * 2 * amp * N / 2
 
 
+def measured_traffic():
+    """HBM bytes per launch of the dense sweep from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (scaled by a plain copy of known size), or
+    None if the sweep source changed since the counters were taken."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "dense_sweep_c128_30q_pmc.json")
+    src = os.path.join(ROOT, "paper_1604_06460_amd", "csrc", "sweep.hip")
+    try:
+        d = json.load(open(rec))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return d["traffic_bytes_per_launch"] if h == d.get("sweep_hip_sha256_prefix") else None
+
+
 def cpu_baseline(n, gates, budget_s=12.0):
     """The CPU oracle (plain gate-by-gate FP64 simulator) applying the first
     gates of the same circuit to |0...0>; stops after ~budget_s seconds."""
@@ -176,7 +191,7 @@ def main():
     sweep_ms = part_ms["fused"] / n_blocks
     achieved = 2 * amp * N / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "k_dense<double,4> (fused 4-qubit block sweep)",
                 "avg_launch_ms": round(sweep_ms, 4), "bytes_per_launch": 2 * amp * N}
 
