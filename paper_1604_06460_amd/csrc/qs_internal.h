@@ -92,6 +92,9 @@ int launch_diag(qs_state *h, const GateDesc &d, const void *dmat, int stride /*r
 int launch_phase1(qs_state *h, const GateDesc &d, const void *dmat);
 int launch_monomial(qs_state *h, const GateDesc &d, const void *dmat);
 int launch_cast_f64_to_f32(hipStream_t s, const double *src, float *dst, size_t count);
+// FP32 MFMA path for dense 6-qubit blocks on complex64 states (mfma.hip)
+bool mfma_applicable(const qs_state *h, const GateDesc &d);
+int launch_dense_mfma(qs_state *h, const GateDesc &d, const void *dmat);
 int launch_set_basis(qs_state *h, uint64_t index);
 
 // Enqueue one gate whose FP64 matrix is on the host (uploads, casts).

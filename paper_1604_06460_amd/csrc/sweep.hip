@@ -369,6 +369,10 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
     const IT n_groups = IT(h->dim() >> np);
     C2 *psi = static_cast<C2 *>(h->psi);
     const R *m = static_cast<const R *>(dmat);
+    // 6-qubit blocks on complex64 states: batched GEMM on the matrix cores
+    if constexpr (sizeof(R) == 4 && K == 6) {
+        if (mfma_applicable(h, d)) return launch_dense_mfma(h, d, dmat);
+    }
     // targets inside a 128-byte line: stage the tile through LDS
     constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
     constexpr bool lds_capable = (sizeof(R) == 8) ? (K <= 5) : (K <= 6);
