@@ -261,6 +261,112 @@ int qs_expectation(qs_handle h, uint64_t x_mask, uint64_t y_mask, uint64_t z_mas
 int qs_measure(qs_handle h, int m, const int *qubits, int shots, const double *uniforms,
                uint64_t *outcomes, double *probs_or_null, int collapse);
 
+/* ---------------------------------------------------------------------- */
+/* Batches: many independent complex64 circuits in one persistent launch  */
+/* ---------------------------------------------------------------------- */
+
+/* Segment kinds. Every segment carries its gate-level form; QFT and modmul
+ * segments also carry the subroutine description the emulator uses instead
+ * (Sec. III: the emulator "only has to return the same result"). */
+enum qs_seg_kind { QS_SEG_GATES = 0, QS_SEG_QFT = 1, QS_SEG_MODMUL = 2 };
+
+/* Per-segment plan options: fuse the gate-level form into blocks of at most
+ * 2, 4 or 6 qubits, or run the emulated subroutine (QFT as an FFT,
+ * modmul as a basis-state permutation; not valid for QS_SEG_GATES). */
+enum qs_plan_option { QS_PLAN_K2 = 0, QS_PLAN_K4 = 1, QS_PLAN_K6 = 2, QS_PLAN_EMULATE = 3 };
+
+/* Features per segment returned by qs_batch_features. */
+#define QS_N_FEATURES 24
+
+typedef struct qs_segment {
+    int kind;
+    qs_circuit gates;      /* gate-level form (all kinds) */
+    int q_lo, m, inverse;  /* QS_SEG_QFT: field and direction, as qs_emulate_qft */
+    qs_perm perm;          /* QS_SEG_MODMUL: kind QS_PERM_MODMUL, as qs_emulate_permutation;
+                              the gate form must agree with it on the states it meets */
+} qs_segment;
+
+typedef struct qs_batch_circuit {
+    int n_qubits;          /* 2 .. 26 */
+    int n_segments;
+    const qs_segment *segments;
+} qs_batch_circuit;
+
+typedef struct qs_batch_t *qs_batch;
+
+/* Copy the circuits (every circuit starts from |0...0>, complex64) and
+ * allocate their states on the current device. Gate lists shared by
+ * several segments (same array pointers) are stored once. */
+int qs_batch_create(int n_circuits, const qs_batch_circuit *circuits, void *hip_stream,
+                    qs_batch *out);
+
+/* Total segment count (segments are numbered circuit by circuit, in order)
+ * and total state bytes. */
+int qs_batch_info(qs_batch b, int *n_segments, double *state_bytes);
+
+/* Per segment (any pointer may be NULL): kind, owning circuit, qubits. */
+int qs_batch_segment_info(qs_batch b, int *kind, int *circuit, int *n_qubits);
+
+/* QS_N_FEATURES floats per segment describing it for the cost model: size,
+ * kind, gate statistics, fused block counts at k = 2, 4, 6, LDS residency,
+ * estimated bytes and flops. */
+int qs_batch_features(qs_batch b, float *features);
+
+/* Choose one qs_plan_option per segment: fuses (host plan, FP64 GPU
+ * composition, cached per gate list and k) and builds the op lists. */
+int qs_batch_set_plan(qs_batch b, const int *options);
+
+/* Run every circuit in one persistent launch. wall_ms: launch time
+ * (HIP events); seg_us (per segment, optional): device time of each segment
+ * from the in-kernel real-time counter; norms / z0 (per circuit, optional):
+ * sum |a|^2 and <Z_0>, FP64 accumulated. */
+int qs_batch_run(qs_batch b, double *wall_ms, double *seg_us, double *norms, double *z0);
+
+/* Copy circuit c's final state (2^n complex64) to the host. */
+int qs_batch_get_state(qs_batch b, int circuit, void *host_dst);
+
+int qs_batch_free(qs_batch b);
+
+/* ---------------------------------------------------------------------- */
+/* Learned cost model and plan choice                                      */
+/* ---------------------------------------------------------------------- */
+
+/* A 24 -> 64 -> 64 -> 4 perceptron (ReLU, FP32) predicting the log device
+ * time of a segment under each qs_plan_option. Parameters, 6020 floats:
+ * W1[24][64], b1[64], W2[64][64], b2[64], W3[64][4], b3[4], row-major with
+ * y = relu(relu(x W1 + b1) W2 + b2) W3 + b3. Inputs are standardised as
+ * (x - mean) * inv_std before W1. Forward, backward and Adam run in the
+ * library's kernels on the model's stream. */
+#define QS_MLP_PARAMS 6020
+typedef struct qs_mlp_t *qs_mlp;
+
+/* params == NULL: He-initialised weights from `seed`, zero biases. */
+int qs_mlp_create(const float *params, uint64_t seed, void *hip_stream, qs_mlp *out);
+int qs_mlp_get_params(qs_mlp m, float *params);
+int qs_mlp_set_norm(qs_mlp m, const float *mean, const float *inv_std);
+/* y[n][4] for x[n][24] (host arrays). */
+int qs_mlp_forward(qs_mlp m, int n, const float *x, float *y);
+/* Loss sum(mask (y - t)^2) / sum(mask) and its gradient (6020 floats). */
+int qs_mlp_loss_grad(qs_mlp m, int n, const float *x, const float *t, const float *mask,
+                     float *loss, float *grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the gradient of the
+ * last qs_mlp_loss_grad / training minibatch. */
+int qs_mlp_adam_step(qs_mlp m, float lr);
+/* Mini-batch Adam over `epochs` shuffled passes; final_loss on all rows. */
+int qs_mlp_train(qs_mlp m, int n, const float *x, const float *t, const float *mask, int epochs,
+                 int batch, float lr, uint64_t seed, float *final_loss);
+int qs_mlp_free(qs_mlp m);
+
+/* Plan choice for every segment of a batch:
+ *   QS_POLICY_FIXED_K2/K4/K6: fuse gate lists at k, emulate subroutines;
+ *   QS_POLICY_HEURISTIC: arithmetic emulated (Sec. III-A, IV-B); QFT
+ *     emulated when Eq. (1) (one device, no exchange) beats Eq. (2); gate
+ *     lists fused at the width with the lowest roofline estimate;
+ *   QS_POLICY_LEARNED: the option with the smallest predicted time. */
+enum qs_policy { QS_POLICY_HEURISTIC = 0, QS_POLICY_LEARNED = 1, QS_POLICY_FIXED_K2 = 2,
+                 QS_POLICY_FIXED_K4 = 3, QS_POLICY_FIXED_K6 = 4 };
+int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
+
 #ifdef __cplusplus
 }
 #endif

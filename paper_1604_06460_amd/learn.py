@@ -1,0 +1,82 @@
+"""Training data from self-measured timings, fitting, and the learned-vs-plain
+comparison for batches.
+
+Orchestration only: features, plans, the batched launch, the per-segment
+timings (in-kernel real-time counter) and the model's forward, backward and
+Adam steps all run inside libqs.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import qs as Q
+
+PLAIN = {
+    "heuristic": Q.QS_POLICY_HEURISTIC,
+    "fixed_k2": Q.QS_POLICY_FIXED_K2,
+    "fixed_k4": Q.QS_POLICY_FIXED_K4,
+    "fixed_k6": Q.QS_POLICY_FIXED_K6,
+}
+
+
+def random_options(kinds, rng):
+    """A random valid option per segment (emulation only for subroutines)."""
+    hi = np.where(kinds == Q.QS_SEG_GATES, 3, 4)
+    return (rng.random(kinds.size) * hi).astype(np.int32)
+
+
+def collect(batch, runs, seed, with_policies=True):
+    """Run `batch` under `runs` random plans (plus the plain policies) and
+    return (X, T, mask): features, mean natural-log device microseconds per
+    option, and which options were measured."""
+    rng = np.random.default_rng(seed)
+    kinds, _, _ = batch.segment_info()
+    X = batch.features()
+    n = batch.n_segments
+    s = np.zeros((n, 4))
+    c = np.zeros((n, 4))
+    plans = [random_options(kinds, rng) for _ in range(runs)]
+    if with_policies:
+        plans += [Q.choose(batch, p) for p in PLAIN.values()]
+    idx = np.arange(n)
+    for opts in plans:
+        batch.set_plan(opts)
+        batch.run()                      # first run after a plan: warm
+        _, seg_us, _, _ = batch.run()
+        s[idx, opts] += np.log(np.maximum(seg_us, 1e-3))
+        c[idx, opts] += 1
+    mask = (c > 0).astype(np.float32)
+    T = np.where(c > 0, s / np.maximum(c, 1), 0.0).astype(np.float32)
+    return X, T, mask
+
+
+def fit(X, T, mask, epochs=80, batch=256, lr=2e-3, seed=0):
+    """Standardise the features and train the model with Adam."""
+    mean = X.mean(0)
+    std = X.std(0)
+    inv = 1.0 / np.where(std > 1e-6, std, 1.0)
+    m = Q.Mlp(seed=seed)
+    m.set_norm(mean, inv)
+    loss = m.train(X, T, mask, epochs, batch, lr, seed)
+    return m, loss
+
+
+def wall_times(batch, model, repeats=3):
+    """Median wall time (ms) of one launch per policy, and the plans."""
+    res, plans = {}, {}
+    pols = dict(PLAIN)
+    if model is not None:
+        pols = {"learned": Q.QS_POLICY_LEARNED, **pols}
+    for name, pol in pols.items():
+        opts = Q.choose(batch, pol, model if pol == Q.QS_POLICY_LEARNED else None)
+        batch.set_plan(opts)
+        batch.run()
+        res[name] = float(np.median([batch.run()[0] for _ in range(repeats)]))
+        plans[name] = opts
+    return res, plans
+
+
+def learned_vs_plain(res):
+    best = min(v for k, v in res.items() if k != "learned")
+    best_name = min((v, k) for k, v in res.items() if k != "learned")[1]
+    return res["learned"] / best, best_name

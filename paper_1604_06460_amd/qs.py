@@ -47,6 +47,20 @@ class Perm(C.Structure):
                 ("a", _U64), ("N", _U64), ("lo", _I), ("nbits", _I), ("dest", _P)]
 
 
+class Segment(C.Structure):
+    _fields_ = [("kind", _I), ("gates", Circuit), ("q_lo", _I), ("m", _I), ("inverse", _I),
+                ("perm", Perm)]
+
+
+class BatchCircuit(C.Structure):
+    _fields_ = [("n_qubits", _I), ("n_segments", _I), ("segments", _P)]
+
+
+QS_SEG_GATES, QS_SEG_QFT, QS_SEG_MODMUL = 0, 1, 2
+QS_PLAN_K2, QS_PLAN_K4, QS_PLAN_K6, QS_PLAN_EMULATE = 0, 1, 2, 3
+QS_N_FEATURES = 24
+
+
 def _sig(name, args, res=_I):
     f = getattr(_L, name)
     f.argtypes = args
@@ -79,6 +93,95 @@ _sig("qs_emulate_permutation", [_P, C.POINTER(Perm)])
 _sig("qs_norm2", [_P, C.POINTER(_D)])
 _sig("qs_expectation", [_P, _U64, _U64, _U64, C.POINTER(_D), C.POINTER(_D)])
 _sig("qs_measure", [_P, _I, _P, _I, _P, _P, _P, _I])
+_sig("qs_batch_create", [_I, _P, _P, C.POINTER(_P)])
+_sig("qs_batch_info", [_P, C.POINTER(_I), C.POINTER(_D)])
+_sig("qs_batch_segment_info", [_P, _P, _P, _P])
+_sig("qs_batch_features", [_P, _P])
+_sig("qs_batch_set_plan", [_P, _P])
+_sig("qs_batch_run", [_P, C.POINTER(_D), _P, _P, _P])
+_sig("qs_batch_get_state", [_P, _I, _P])
+_sig("qs_batch_free", [_P])
+_sig("qs_mlp_create", [_P, _U64, _P, C.POINTER(_P)])
+_sig("qs_mlp_get_params", [_P, _P])
+_sig("qs_mlp_set_norm", [_P, _P, _P])
+_sig("qs_mlp_forward", [_P, _I, _P, _P])
+_sig("qs_mlp_loss_grad", [_P, _I, _P, _P, _P, C.POINTER(C.c_float), _P])
+_sig("qs_mlp_adam_step", [_P, C.c_float])
+_sig("qs_mlp_train", [_P, _I, _P, _P, _P, _I, _I, C.c_float, _U64, C.POINTER(C.c_float)])
+_sig("qs_mlp_free", [_P])
+_sig("qs_batch_choose", [_P, _I, _P, _P])
+
+QS_MLP_PARAMS = 6020
+QS_POLICY_HEURISTIC, QS_POLICY_LEARNED, QS_POLICY_FIXED_K2, QS_POLICY_FIXED_K4, QS_POLICY_FIXED_K6 = range(5)
+
+
+class Mlp:
+    """The 24-64-64-4 cost model; every computation runs in libqs kernels."""
+
+    def __init__(self, params=None, seed=0, stream=None):
+        h = _P()
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        _chk(_L.qs_mlp_create(_ptr(p), int(seed), stream, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        out = np.zeros(QS_MLP_PARAMS, dtype=np.float32)
+        _chk(_L.qs_mlp_get_params(self._h, _ptr(out)))
+        return out
+
+    def set_norm(self, mean, inv_std):
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(inv_std, dtype=np.float32)
+        _chk(_L.qs_mlp_set_norm(self._h, _ptr(m), _ptr(s)))
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros((x.shape[0], 4), dtype=np.float32)
+        _chk(_L.qs_mlp_forward(self._h, x.shape[0], _ptr(x), _ptr(y)))
+        return y
+
+    def loss_grad(self, x, t, mask):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        mk = np.ascontiguousarray(mask, dtype=np.float32)
+        g = np.zeros(QS_MLP_PARAMS, dtype=np.float32)
+        loss = C.c_float()
+        _chk(_L.qs_mlp_loss_grad(self._h, x.shape[0], _ptr(x), _ptr(t), _ptr(mk), C.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def adam_step(self, lr):
+        _chk(_L.qs_mlp_adam_step(self._h, float(lr)))
+
+    def train(self, x, t, mask, epochs, batch, lr, seed=0):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        mk = np.ascontiguousarray(mask, dtype=np.float32)
+        loss = C.c_float()
+        _chk(_L.qs_mlp_train(self._h, x.shape[0], _ptr(x), _ptr(t), _ptr(mk), int(epochs), int(batch),
+                             float(lr), int(seed), C.byref(loss)))
+        return loss.value
+
+    def free(self):
+        if self._h:
+            _L.qs_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def choose(batch, policy, model=None):
+    """Per-segment plan options for a Batch under a policy."""
+    out = np.zeros(batch.n_segments, dtype=np.int32)
+    _chk(_L.qs_batch_choose(batch._h, int(policy), model.handle if model is not None else None, _ptr(out)))
+    return out
 
 
 class QSError(RuntimeError):
@@ -296,3 +399,90 @@ class State:
         _chk(_L.qs_measure(self._h, int(q.size), _ptr(q), int(u.size), _ptr(u) if u.size else None,
                            _ptr(outc), _ptr(probs), int(bool(collapse))))
         return outc[:u.size].copy(), probs
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent complex64 circuits (one persistent launch)
+# ---------------------------------------------------------------------------
+class Batch:
+    """circuits: objects with .n and .segments; each segment has .kind,
+    .gates (gate list), and for QFT segments .q_lo/.m/.inverse, for modmul
+    segments .modmul = (work_lo, w, ctrl_lo, c, a, N). Gate lists that are
+    the same Python object are passed once."""
+
+    def __init__(self, circuits, stream=None):
+        packed = {}
+        self._keep = []
+        seg_arrays = []
+        cs = (BatchCircuit * len(circuits))()
+        for ci, c in enumerate(circuits):
+            segs = (Segment * len(c.segments))()
+            for si, s in enumerate(c.segments):
+                key = id(s.gates)
+                if key not in packed:
+                    packed[key] = (PackedCircuit(s.gates), s.gates)
+                pc = packed[key][0]
+                segs[si].kind = int(s.kind)
+                segs[si].gates = pc.c
+                if s.kind == QS_SEG_QFT:
+                    segs[si].q_lo, segs[si].m, segs[si].inverse = int(s.q_lo), int(s.m), int(bool(s.inverse))
+                elif s.kind == QS_SEG_MODMUL:
+                    wl, w, cl, cc, a, N = s.modmul
+                    segs[si].perm = Perm(QS_PERM_MODMUL, int(wl), int(w), int(cl), int(cc), int(a), int(N), 0, 0, None)
+            seg_arrays.append(segs)
+            cs[ci].n_qubits = int(c.n)
+            cs[ci].n_segments = len(c.segments)
+            cs[ci].segments = C.cast(segs, _P)
+        h = _P()
+        _chk(_L.qs_batch_create(len(circuits), C.cast(cs, _P), stream, C.byref(h)))
+        self._h = h
+        self.n_circuits = len(circuits)
+        self.ns = [int(c.n) for c in circuits]
+        # the library copied everything it needs
+        del packed, seg_arrays
+        nseg, sb = _I(), _D()
+        _chk(_L.qs_batch_info(h, C.byref(nseg), C.byref(sb)))
+        self.n_segments = nseg.value
+        self.state_bytes = sb.value
+
+    def segment_info(self):
+        kind = np.zeros(self.n_segments, dtype=np.int32)
+        circ = np.zeros(self.n_segments, dtype=np.int32)
+        nq = np.zeros(self.n_segments, dtype=np.int32)
+        _chk(_L.qs_batch_segment_info(self._h, _ptr(kind), _ptr(circ), _ptr(nq)))
+        return kind, circ, nq
+
+    def features(self):
+        f = np.zeros((self.n_segments, QS_N_FEATURES), dtype=np.float32)
+        _chk(_L.qs_batch_features(self._h, _ptr(f)))
+        return f
+
+    def set_plan(self, options):
+        o = np.ascontiguousarray(options, dtype=np.int32)
+        if o.size != self.n_segments:
+            raise ValueError("one option per segment")
+        _chk(_L.qs_batch_set_plan(self._h, _ptr(o)))
+
+    def run(self):
+        ms = _D()
+        seg = np.zeros(self.n_segments, dtype=np.float64)
+        norms = np.zeros(self.n_circuits, dtype=np.float64)
+        z0 = np.zeros(self.n_circuits, dtype=np.float64)
+        _chk(_L.qs_batch_run(self._h, C.byref(ms), _ptr(seg), _ptr(norms), _ptr(z0)))
+        return ms.value, seg, norms, z0
+
+    def state(self, c):
+        out = np.empty(1 << self.ns[c], dtype=np.complex64)
+        _chk(_L.qs_batch_get_state(self._h, int(c), _ptr(out)))
+        return out
+
+    def free(self):
+        if self._h:
+            _L.qs_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

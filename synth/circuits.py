@@ -335,6 +335,125 @@ def modmul_gate_circuit(w: int, c: int, a: int, N: int):
     return gates, L
 
 
+_MODMUL_CACHE = {}
+
+
+def modmul_gate_circuit_on(x, acc, kreg, carry, flag, ctrl, a, N):
+    """The same Toffoli network as modmul_gate_circuit on explicit qubit
+    lists (x: w qubits, acc/kreg: w+1 qubits, ctrl: c qubits). Identical
+    requests return the same (shared, read-only) gate list."""
+    key = (tuple(x), tuple(acc), tuple(kreg), int(carry), int(flag), tuple(ctrl), int(a), int(N))
+    hit = _MODMUL_CACHE.get(key)
+    if hit is None:
+        hit = _modmul_gates_on(x, acc, kreg, carry, flag, ctrl, a, N)
+        _MODMUL_CACHE[key] = hit
+    return hit
+
+
+def _modmul_gates_on(x, acc, kreg, carry, flag, ctrl, a, N):
+    w, c = len(x), len(ctrl)
+    L = ModmulLayout(w, c, list(x), list(acc), list(kreg), int(carry), int(flag), list(ctrl))
+    gates = []
+    for j in range(c):
+        aj = pow(a, 1 << j, N)
+        aj_inv = pow(aj, -1, N)
+        cj = L.ctrl[j]
+        gates += _mul_into_acc(L, aj, N, cj)
+        for i in range(w):
+            gates += [cnot(L.acc[i], L.x[i]), mcx((cj, L.x[i]), L.acc[i]),
+                      cnot(L.acc[i], L.x[i])]
+        gates += inverse_circuit(_mul_into_acc(L, aj_inv, N, cj))
+    return gates
+
+
+def random_layer_on(qubits, rng):
+    """One random layer restricted to `qubits`: a Haar 2x2 on each (in the
+    listed order), then CZ on disjoint pairs of a random permutation."""
+    nq = len(qubits)
+    z = (rng.standard_normal((nq, 2, 2)) + 1j * rng.standard_normal((nq, 2, 2))) * _S2
+    qm, rm = np.linalg.qr(z)
+    d = np.diagonal(rm, axis1=1, axis2=2)
+    us = qm * (d / np.abs(d))[:, None, :]
+    gates = [Gate((int(q),), us[i], name="U") for i, q in enumerate(qubits)]
+    perm = rng.permutation(nq)
+    for j in range(len(qubits) // 2):
+        gates.append(cz(qubits[perm[2 * j]], qubits[perm[2 * j + 1]]))
+    return gates
+
+
+# Segment kinds of the batched workload
+SEG_LAYER, SEG_QFT, SEG_MODMUL = 0, 1, 2
+
+
+@dataclass
+class Segment:
+    kind: int
+    gates: list                 # gate-level form (always present)
+    q_lo: int = 0               # QFT field
+    m: int = 0
+    inverse: bool = False
+    modmul: tuple = ()          # (work_lo, w, ctrl_lo, c, a, N)
+
+
+@dataclass
+class BatchCircuit:
+    n: int
+    segments: list
+
+
+def batch_mix(count: int, seed: int, n_range=(10, 22), d_range=(10, 60),
+              p_qft=0.1, p_modmul=0.1):
+    """Uneven batch of independent circuits: n ~ U{n_range}, depth ~
+    U{d_range} slots; each slot is a random layer (on the data qubits), a
+    QFT on a random contiguous range of m >= 3 data qubits, or a controlled
+    modular multiplication.
+
+    A circuit with n >= 16 that draws any modmul slot reserves its top
+    qubits for arithmetic: a w-qubit work register x (w = 3 from n >= 20,
+    else 2), a 2-qubit control register and 2w+4 clean ancillas, so that a
+    gate-level Toffoli form exists. A preparation segment sets x = 1 and puts
+    the control register in uniform superposition; only modmul slots touch
+    these qubits afterwards, so x < N always holds and the gate-level and
+    emulated forms agree exactly (the modular exponentiation structure of
+    Shor's algorithm, Sec. III). Smaller circuits turn modmul slots into
+    random layers."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        depth = int(rng.integers(d_range[0], d_range[1] + 1))
+        kinds = rng.choice(3, size=depth, p=[1 - p_qft - p_modmul, p_qft, p_modmul])
+        use_mm = n >= 16 and bool((kinds == SEG_MODMUL).any())
+        w, c = (3 if n >= 20 else 2), 2
+        n_data = n - (3 * w + c + 4) if use_mm else n
+        data = list(range(n_data))
+        xq = list(range(n_data, n_data + w))
+        cq = list(range(n_data + w, n_data + w + c))
+        anc = list(range(n_data + w + c, n))
+        segs = []
+        if use_mm:
+            prep = [g1(MAT_X, xq[0], "X")] + [g1(MAT_H, q, "H") for q in cq]
+            segs.append(Segment(SEG_LAYER, prep))
+        for kd in kinds:
+            if kd == SEG_MODMUL and not use_mm:
+                kd = SEG_LAYER
+            if kd == SEG_LAYER:
+                segs.append(Segment(SEG_LAYER, random_layer_on(data, rng)))
+            elif kd == SEG_QFT:
+                m = int(rng.integers(3, n_data + 1))
+                q_lo = int(rng.integers(0, n_data - m + 1))
+                inv = bool(rng.integers(0, 2))
+                segs.append(Segment(SEG_QFT, qft_circuit(m, q_lo, inverse=inv), q_lo, m, inv))
+            else:
+                a, N = modmul_params(w, int(rng.integers(0, 2 ** 31)))
+                acc, kreg = anc[0:w + 1], anc[w + 1:2 * w + 2]
+                carry, flag = anc[2 * w + 2], anc[2 * w + 3]
+                g = modmul_gate_circuit_on(xq, acc, kreg, carry, flag, cq, a, N)
+                segs.append(Segment(SEG_MODMUL, g, modmul=(xq[0], w, cq[0], c, a, N)))
+        out.append(BatchCircuit(n, segs))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Flat packing of gate lists for C interfaces
 # ---------------------------------------------------------------------------

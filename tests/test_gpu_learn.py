@@ -1,0 +1,105 @@
+"""The learned cost model on the GPU: its FP32 forward/backward/Adam kernels
+against the FP64 NumPy oracle, and the learned plan choice against the plain
+policies on a held-out batch (results must stay exact, time must not get
+worse)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_1604_06460_amd import qs
+    return qs
+
+
+def _split(flat):
+    shapes = [(24, 64), (64,), (64, 64), (64,), (64, 4), (4,)]
+    out, o = [], 0
+    for s in shapes:
+        k = int(np.prod(s))
+        out.append(flat[o:o + k].reshape(s).astype(np.float64))
+        o += k
+    return out
+
+
+def _data(rng, n):
+    X = rng.standard_normal((n, 24)).astype(np.float32)
+    T = rng.standard_normal((n, 4)).astype(np.float32)
+    mask = (rng.random((n, 4)) < 0.7).astype(np.float32)
+    mask[:, 0] = 1
+    return X, T, mask
+
+
+def test_forward_loss_and_gradient_vs_fp64_oracle(Q, O):
+    rng = np.random.default_rng(3)
+    m = Q.Mlp(seed=11)
+    p = m.params()
+    # nonzero biases so every gradient path is exercised
+    p = p + 0.05 * rng.standard_normal(p.size).astype(np.float32)
+    m.free()
+    m = Q.Mlp(params=p)
+    X, T, mask = _data(rng, 777)
+    ref = O.MLP(_split(p.astype(np.float64)))
+    y = m.forward(X)
+    y_ref, _ = ref.forward(X.astype(np.float64))
+    assert np.abs(y - y_ref).max() < 1e-4 * max(1.0, np.abs(y_ref).max())
+    loss, g = m.loss_grad(X, T, mask)
+    l_ref = ref.loss(X.astype(np.float64), T, mask)
+    g_ref = np.concatenate([a.reshape(-1) for a in ref.grads(X.astype(np.float64), T, mask)])
+    assert abs(loss - l_ref) < 1e-4 * max(1.0, abs(l_ref))
+    rel = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    assert rel < 1e-4, rel
+
+
+def test_adam_step_vs_oracle(Q, O):
+    rng = np.random.default_rng(4)
+    m = Q.Mlp(seed=5)
+    p0 = m.params().astype(np.float64)
+    X, T, mask = _data(rng, 300)
+    _, g = m.loss_grad(X, T, mask)
+    m.adam_step(1e-3)
+    p1 = m.params()
+    params = [p0.copy()]
+    O.MLP.adam(params, [g.astype(np.float64)], [np.zeros_like(p0)], [np.zeros_like(p0)], 1, lr=1e-3)
+    assert np.abs(p1 - params[0]).max() < 1e-6
+
+
+def test_training_fits_a_smooth_target(Q):
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((4000, 24)).astype(np.float32)
+    W = rng.standard_normal((24, 4)) * 0.3
+    T = (np.tanh(X @ W) + 0.1 * X[:, :4] ** 2).astype(np.float32)
+    mask = np.ones_like(T)
+    m = Q.Mlp(seed=1)
+    l0, _ = m.loss_grad(X, T, mask)
+    lf = m.train(X, T, mask, epochs=30, batch=128, lr=3e-3, seed=2)
+    assert lf < 0.1 * l0, (l0, lf)
+
+
+def test_learned_plan_choice_on_held_out_batch(Q, O, S):
+    """Train on timings of one batch, choose plans for a disjoint batch:
+    the learned plans give the oracle's states and run no slower (within
+    measurement noise) than the best plain policy."""
+    from paper_1604_06460_amd import learn
+    train = Q.Batch(S.batch_mix(160, S.SEED_BASE * 1000 + 500000, n_range=(10, 20), d_range=(6, 20)))
+    X, T, mask = learn.collect(train, runs=4, seed=1)
+    train.free()
+    model, loss = learn.fit(X, T, mask, epochs=60)
+    assert np.isfinite(loss)
+    circuits = S.batch_mix(160, S.SEED_BASE * 1000 + 7, n_range=(10, 20), d_range=(6, 20))
+    ev = Q.Batch(circuits)
+    res, plans = learn.wall_times(ev, model, repeats=3)
+    ratio, best = learn.learned_vs_plain(res)
+    print("wall ms per policy:", res, "learned / best plain (%s) = %.3f" % (best, ratio))
+    assert ratio < 1.15
+    # results are exact under the learned plan
+    ev.set_plan(plans["learned"])
+    ev.run()
+    from test_gpu_batch import oracle_circuit
+    for c in range(0, len(circuits), 23):
+        if circuits[c].n <= 16:
+            ref = oracle_circuit(O, S, circuits[c])
+            assert np.abs(ev.state(c).astype(np.complex128) - ref).max() < 1e-5
+    ev.free()
