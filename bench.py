@@ -44,6 +44,14 @@ def qft_gate_bytes(n, amp):
     return n * 2 * amp * N + n_cr * 2 * amp * N / 4 + (n // 2) * 2 * amp * N / 2
 
 
+T_START = time.perf_counter()
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print("[bench %6.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
 def measured_traffic():
     """HBM bytes per launch of the dense sweep from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (scaled by a plain copy of known size), or
@@ -80,6 +88,56 @@ def cpu_baseline(n, gates, budget_s=12.0):
                       "from |0...0>, complex128, %.1f s" % (done, DEPTH, n, dt)}
 
 
+def batch_learned(Q, S):
+    """4096 uneven circuits (n ~ U{10..22}, depth ~ U{10..60}; random
+    layers, QFTs, modular multiplications) in one persistent launch per
+    policy. The cost model is trained on timings of a disjoint 512-circuit
+    batch; every policy is timed on the 4096-circuit batch (median of 3
+    launches), and the learned plan's states are checked against the oracle
+    on sampled circuits."""
+    from oracle import oracle as O
+    from paper_1604_06460_amd import learn
+    t0 = time.perf_counter()
+    train = Q.Batch(S.batch_mix(512, S.SEED_BASE * 1000 + 500000))
+    log("training batch created: %d segments" % train.n_segments)
+    X, T, mask = learn.collect(train, runs=4, seed=1, log=log)
+    train.free()
+    model, loss = learn.fit(X, T, mask, epochs=60)
+    t_train = time.perf_counter() - t0
+    log("cost model trained: %d rows, loss %.4f" % (X.shape[0], loss))
+    circuits = S.batch_mix(4096, S.SEED_BASE + 4)
+    log("4096-circuit batch generated")
+    ev = Q.Batch(circuits)
+    log("4096-circuit batch created: %d segments, %.1f GB of states" % (ev.n_segments, ev.state_bytes / 1e9))
+    res, plans = learn.wall_times(ev, model, repeats=3, log=log)
+    ratio, best = learn.learned_vs_plain(res)
+    ev.set_plan(plans["learned"])
+    ev.run()
+    err = 0.0
+    checked = 0
+    for c in range(0, len(circuits), 97):
+        if circuits[c].n <= 16:
+            psi = S.zero_state(circuits[c].n)
+            for s in circuits[c].segments:
+                if s.kind == S.SEG_QFT:
+                    psi = O.dft_numpy(psi, s.q_lo, s.m, s.inverse)
+                elif s.kind == S.SEG_MODMUL:
+                    psi = O.modmul(psi, *s.modmul)
+                else:
+                    psi = O.apply_circuit(psi, s.gates)
+            err = max(err, float(np.abs(ev.state(c).astype(np.complex128) - psi).max()))
+            checked += 1
+    ev.free()
+    model.free()
+    return {"circuits": len(circuits), "segments": int(len(plans["learned"])),
+            "wall_ms": {k: round(v, 2) for k, v in res.items()},
+            "learned_vs_best_plain": round(ratio, 4), "best_plain": best,
+            "circuits_per_s_learned": round(len(circuits) / (res["learned"] * 1e-3), 1),
+            "train_rows": int(X.shape[0]), "train_loss": round(float(loss), 5),
+            "train_s": round(t_train, 1),
+            "max_abs_err_vs_oracle": err, "circuits_checked": checked}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +145,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parts", default="all", help="all | fused (profiling runs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain part")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state-vector path is not sharded "
@@ -155,14 +214,17 @@ def main():
         prog.free()
         return z0, nrm
 
-    for _ in range(args.warmup):
+    log("setup done (%d fused blocks)" % n_blocks)
+    for w in range(args.warmup):
         step()
+        log("warmup step %d done" % (w + 1))
     torch.cuda.synchronize()
     part_ms = {}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         z0, nrm = step()
         stream.synchronize()
+        log("timed step %d done" % (k + 1))
         names = list(ev.keys())
         for a, b in zip(names[:-1], names[1:]):
             part_ms.setdefault(b, []).append(ev[a].elapsed_time(ev[b]))
@@ -218,15 +280,20 @@ def main():
     stream.synchronize()
     copy_gbs = 3 * 2 * amp * N / (ev["c0"].elapsed_time(ev["c1"]) * 1e-3) / 1e9
 
+    st.free()
+    del normal
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batch and parts_all:
+        batched = batch_learned(Q, S)
     cpu = None
     if not args.no_cpu_baseline:
-        st.free()
-        del normal
-        torch.cuda.empty_cache()
+        log("cpu baseline (oracle) starts")
         cpu = cpu_baseline(n, gates)
+        log("cpu baseline done")
 
     out = {
-        "metric": "HBM GB/s of gate sweeps at 30q",
+        "metric": "HBM GB/s of gate sweeps at 30q; learned-vs-plain wall time at 1e-5 amp error",
         "value": round(value, 1),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -250,6 +317,7 @@ def main():
                           for k in bytes_part if k in part_ms and part_ms[k] > 0},
         "copy_ceiling_gbs": round(copy_gbs, 1),
         "check": check,
+        "batched_learned": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -25,7 +25,12 @@ def random_options(kinds, rng):
     return (rng.random(kinds.size) * hi).astype(np.int32)
 
 
-def collect(batch, runs, seed, with_policies=True):
+def _say(log, msg):
+    if log is not None:
+        log(msg)
+
+
+def collect(batch, runs, seed, with_policies=True, log=None):
     """Run `batch` under `runs` random plans (plus the plain policies) and
     return (X, T, mask): features, mean natural-log device microseconds per
     option, and which options were measured."""
@@ -39,12 +44,13 @@ def collect(batch, runs, seed, with_policies=True):
     if with_policies:
         plans += [Q.choose(batch, p) for p in PLAIN.values()]
     idx = np.arange(n)
-    for opts in plans:
+    for pi, opts in enumerate(plans):
         batch.set_plan(opts)
         batch.run()                      # first run after a plan: warm
-        _, seg_us, _, _ = batch.run()
+        ms, seg_us, _, _ = batch.run()
         s[idx, opts] += np.log(np.maximum(seg_us, 1e-3))
         c[idx, opts] += 1
+        _say(log, "timing run %d/%d: %.1f ms" % (pi + 1, len(plans), ms))
     mask = (c > 0).astype(np.float32)
     T = np.where(c > 0, s / np.maximum(c, 1), 0.0).astype(np.float32)
     return X, T, mask
@@ -61,7 +67,7 @@ def fit(X, T, mask, epochs=80, batch=256, lr=2e-3, seed=0):
     return m, loss
 
 
-def wall_times(batch, model, repeats=3):
+def wall_times(batch, model, repeats=3, log=None):
     """Median wall time (ms) of one launch per policy, and the plans."""
     res, plans = {}, {}
     pols = dict(PLAIN)
@@ -73,6 +79,7 @@ def wall_times(batch, model, repeats=3):
         batch.run()
         res[name] = float(np.median([batch.run()[0] for _ in range(repeats)]))
         plans[name] = opts
+        _say(log, "policy %s: %.1f ms" % (name, res[name]))
     return res, plans
 
 
