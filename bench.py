@@ -91,16 +91,17 @@ def cpu_baseline(n, gates, budget_s=12.0):
 def batch_learned(Q, S):
     """4096 uneven circuits (n ~ U{10..22}, depth ~ U{10..60}; random
     layers, QFTs, modular multiplications) in one persistent launch per
-    policy. The cost model is trained on timings of a disjoint 512-circuit
-    batch; every policy is timed on the 4096-circuit batch (median of 3
-    launches), and the learned plan's states are checked against the oracle
-    on sampled circuits."""
+    policy. The cost model is trained on in-kernel segment timings of a
+    disjoint 512-circuit batch run under the plain policies and 12
+    perturbations of them; every policy is timed on the 4096-circuit batch
+    (median of 3 launches), and the learned plan's states are checked
+    against the oracle on sampled circuits."""
     from oracle import oracle as O
     from paper_1604_06460_amd import learn
     t0 = time.perf_counter()
     train = Q.Batch(S.batch_mix(512, S.SEED_BASE * 1000 + 500000))
     log("training batch created: %d segments" % train.n_segments)
-    X, T, mask = learn.collect(train, runs=4, seed=1, log=log)
+    X, T, mask = learn.collect(train, runs=12, seed=1, log=log)
     train.free()
     model, loss = learn.fit(X, T, mask, epochs=60)
     t_train = time.perf_counter() - t0

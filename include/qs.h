@@ -267,7 +267,7 @@ int qs_measure(qs_handle h, int m, const int *qubits, int shots, const double *u
 
 /* Segment kinds. Every segment carries its gate-level form; QFT and modmul
  * segments also carry the subroutine description the emulator uses instead
- * (Sec. III: the emulator "only has to return the same result"). */
+ * (Sec. III: an emulator owes the caller the final state, not the gates). */
 enum qs_seg_kind { QS_SEG_GATES = 0, QS_SEG_QFT = 1, QS_SEG_MODMUL = 2 };
 
 /* Per-segment plan options: fuse the gate-level form into blocks of at most
@@ -316,11 +316,28 @@ int qs_batch_features(qs_batch b, float *features);
  * composition, cached per gate list and k) and builds the op lists. */
 int qs_batch_set_plan(qs_batch b, const int *options);
 
-/* Run every circuit in one persistent launch. wall_ms: launch time
+/* Run every circuit in one persistent launch (as many workgroups as are
+ * co-resident). A circuit of at most 13 qubits runs on one workgroup with
+ * its state in LDS; a larger one is swept in HBM by a gang of workgroups
+ * that meet at a cross-workgroup barrier between ops. Gangs are sized from
+ * the plan's cost estimate: just large enough that no circuit outlasts a
+ * quarter of the average work per workgroup (at most a quarter of the
+ * grid, at least 2^12 amplitudes per member). wall_ms: launch time
  * (HIP events); seg_us (per segment, optional): device time of each segment
  * from the in-kernel real-time counter; norms / z0 (per circuit, optional):
- * sum |a|^2 and <Z_0>, FP64 accumulated. */
+ * sum |a|^2 and <Z_0>, FP64 accumulated, summed over gang members in a
+ * fixed order. Returns QS_EDEVICE if a gang barrier waited more than 5 s
+ * (the kernel then gives up and drains; the states are invalid). */
 int qs_batch_run(qs_batch b, double *wall_ms, double *seg_us, double *norms, double *z0);
+
+/* Schedule of the last qs_batch_run, one entry per ticket (a circuit of at
+ * most 13 qubits has one ticket, a gang one per member), in queue order:
+ * start and end time in microseconds from the earliest start, owning
+ * circuit, gang member, and the workgroup that ran it. Writes at most
+ * `capacity` entries (any array may be NULL) and the ticket count to
+ * *n_tickets. */
+int qs_batch_trace(qs_batch b, int capacity, int *n_tickets, double *start_us, double *end_us,
+                   int *circuit, int *member, int *workgroup);
 
 /* Copy circuit c's final state (2^n complex64) to the host. */
 int qs_batch_get_state(qs_batch b, int circuit, void *host_dst);

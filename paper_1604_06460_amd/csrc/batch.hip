@@ -7,13 +7,18 @@
 // Sec. III-A). Planning turns each circuit into a list of ops; the persistent
 // kernel then runs them.
 //
-// Scheduling: workgroups pop whole circuits from a queue ordered by
-// estimated cost (largest first) and run all of a circuit's ops back to
-// back, so no workgroup ever waits for another and every workgroup leaves
-// the loop once the queue is drained. Circuits of at most 13 qubits (64 KiB
-// of complex64) live in LDS from the first op to the last and are written to
-// HBM once; larger circuits are swept in HBM, with a second buffer for the
-// out-of-place ops (last FFT pass, permutation) assigned on the host.
+// Scheduling: workgroups pop tickets from a queue ordered by estimated time
+// per ticket (largest first). Circuits of at most 13 qubits (64 KiB of
+// complex64) have one ticket: one workgroup keeps the state in LDS from the
+// first op to the last and writes it to HBM once. A larger circuit is swept
+// in HBM by a gang of G workgroups (G grows with 2^n), one ticket per
+// member: each op is split over the members, and the members meet at a
+// cross-workgroup barrier (a monotonic arrival counter per circuit) between
+// ops. A gang's tickets are consecutive in the queue, so only the most
+// recently opened gang can be waiting for members, and any workgroup that
+// finishes its work pops exactly those tickets next; with G no larger than
+// the number of co-resident workgroups every gang completes. A second
+// buffer serves the out-of-place ops (last FFT pass, permutation).
 //
 // Every segment's device time is taken with the constant-rate real-time
 // counter at segment boundaries inside the kernel; these timings are what
@@ -58,7 +63,47 @@ struct BOp {
 struct BCirc {
     int n, op0, op1, final_buf;
     uint64_t off_a, off_b;   // element offsets of the two buffers
+    int gang;                // workgroups sweeping this circuit together
+    int p0;                  // first slot of its norm partials
 };
+
+struct Ticket {
+    int circ, member;
+};
+
+constexpr uint64_t kSpinTicks = 500000000ull;   // 5 s of the 100 MHz counter
+
+// Cross-workgroup barrier of a gang of G workgroups. Every thread releases
+// its stores at device scope (L2 write-back) and the workgroup meets; thread
+// 0 arrives on the circuit's counter with a device-scope release and polls
+// it with relaxed loads (an acquire per poll would invalidate the L2 of the
+// XCD over and over) until all G members of this round have arrived; after
+// the workgroup meets again every thread acquires once (L1/L2 invalidate).
+// The counter only grows (round e completes at (e+1)*G arrivals), so it
+// needs no reset between rounds. A wait longer than kSpinTicks sets the
+// error flag; once it is set no barrier waits, so the kernel drains.
+__device__ __forceinline__ void gang_sync(unsigned *bar, unsigned G, unsigned &epoch, unsigned *err)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (epoch + 1u) * G;
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            // after any timeout every barrier gives way at once
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (wall_clock64() - t0 > kSpinTicks) {
+                atomicOr(err, 1u);
+                break;
+            }
+        }
+    }
+    ++epoch;
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
 
 // ---------------------------------------------------------------------------
 // device helpers (all executed by a whole workgroup; st may point to LDS or
@@ -109,7 +154,7 @@ __device__ __forceinline__ void rdot(const float *__restrict__ row, const float2
 }
 
 template <int K>
-__device__ void op_dense(float2 *st, int n, const BOp &op, const float *__restrict__ mat)
+__device__ void op_dense(float2 *st, int n, const BOp &op, const float *__restrict__ mat, uint32_t r, uint32_t G)
 {
     constexpr int D = 1 << K;
     // offset of local index j inside a group (uniform across the workgroup)
@@ -121,7 +166,7 @@ __device__ void op_dense(float2 *st, int n, const BOp &op, const float *__restri
         return o;
     };
     const uint32_t groups = 1u << (n - K);
-    for (uint32_t g = threadIdx.x; g < groups; g += kBT) {
+    for (uint32_t g = r * kBT + threadIdx.x; g < groups; g += G * kBT) {
         float2 *p = st + deposit_zero(g, op.t, K);
         float2 v[D];
 #pragma unroll
@@ -135,10 +180,10 @@ __device__ void op_dense(float2 *st, int n, const BOp &op, const float *__restri
     }
 }
 
-__device__ void op_diag(float2 *st, int n, const BOp &op, const float *__restrict__ mat)
+__device__ void op_diag(float2 *st, int n, const BOp &op, const float *__restrict__ mat, uint32_t r, uint32_t G)
 {
     const int D = 1 << op.k;
-    for (uint32_t i = threadIdx.x; i < (1u << n); i += kBT) {
+    for (uint32_t i = r * kBT + threadIdx.x; i < (1u << n); i += G * kBT) {
         int j = 0;
 #pragma unroll
         for (int m = 0; m < 6; ++m)
@@ -235,30 +280,44 @@ __device__ __forceinline__ uint32_t perm_src(uint32_t i, const BOp &op, const ui
     return (i & ~(wm << op.work_lo)) | (x << op.work_lo);
 }
 
-__global__ void k_reset(unsigned *counter) { *counter = 0; }
+// counter[0]: queue head, counter[1]: error flag, then one barrier counter
+// per circuit
+__global__ void k_reset(unsigned *counter, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counter[i] = 0;
+}
 
 __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2 *__restrict__ B,
                                                    const BCirc *__restrict__ circ,
-                                                   const int *__restrict__ order, int n_circ,
+                                                   const Ticket *__restrict__ tickets, int n_tickets,
                                                    const BOp *__restrict__ ops,
                                                    const float *__restrict__ pool,
                                                    const PassArgs *__restrict__ passes,
                                                    unsigned *__restrict__ counter,
                                                    uint64_t *__restrict__ seg_ticks,
-                                                   double *__restrict__ norms, double *__restrict__ z0)
+                                                   double2 *__restrict__ partials,
+                                                   double *__restrict__ norms, double *__restrict__ z0,
+                                                   ulonglong2 *__restrict__ trace)
 {
     extern __shared__ unsigned char lds_raw[];
     __shared__ int s_idx;
     __shared__ uint32_t s_tbl[64];
     __shared__ double s_red[2][kBT / 64];
+    unsigned *const err = counter + 1;
+    unsigned *const bars = counter + 2;
     for (;;) {
         if (threadIdx.x == 0) s_idx = int(atomicAdd(counter, 1u));
         __syncthreads();
         const int qi = __builtin_amdgcn_readfirstlane(s_idx);
         __syncthreads();
-        if (qi >= n_circ) break;
-        const BCirc cc = circ[order[qi]];
+        if (qi >= n_tickets) break;
+        const Ticket tk = tickets[qi];
+        const BCirc cc = circ[tk.circ];
+        const uint32_t G = uint32_t(cc.gang), r = uint32_t(tk.member);
         const bool in_lds = cc.n <= kNS;
+        const bool lead = r == 0 && threadIdx.x == 0;
+        const uint64_t t_ticket = wall_clock64();
+        unsigned epoch = 0;
         float2 *const buf_a = A + cc.off_a, *const buf_b = B + cc.off_b;
         float2 *lst = reinterpret_cast<float2 *>(lds_raw);
         int cur_seg = -1;
@@ -266,7 +325,7 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2
         for (int o = cc.op0; o < cc.op1; ++o) {
             const BOp op = ops[o];
             if (op.seg != cur_seg) {
-                if (threadIdx.x == 0) {
+                if (lead) {
                     const uint64_t now = wall_clock64();
                     if (cur_seg >= 0) seg_ticks[cur_seg] = now - t_seg;
                     t_seg = now;
@@ -277,29 +336,30 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2
             float2 *dst = in_lds ? lst : (op.dst ? buf_b : buf_a);
             switch (op.type) {
             case OP_INIT:
-                for (uint32_t i = threadIdx.x; i < (1u << cc.n); i += kBT) dst[i] = float2{i == 0 ? 1.f : 0.f, 0.f};
+                for (uint32_t i = r * kBT + threadIdx.x; i < (1u << cc.n); i += G * kBT)
+                    dst[i] = float2{i == 0 ? 1.f : 0.f, 0.f};
                 break;
             case OP_DENSE: {
                 const float *m = pool + op.mat;
                 switch (op.k) {
-                case 1: op_dense<1>(dst, cc.n, op, m); break;
-                case 2: op_dense<2>(dst, cc.n, op, m); break;
-                case 3: op_dense<3>(dst, cc.n, op, m); break;
-                case 4: op_dense<4>(dst, cc.n, op, m); break;
-                case 5: op_dense<5>(dst, cc.n, op, m); break;
-                default: op_dense<6>(dst, cc.n, op, m); break;
+                case 1: op_dense<1>(dst, cc.n, op, m, r, G); break;
+                case 2: op_dense<2>(dst, cc.n, op, m, r, G); break;
+                case 3: op_dense<3>(dst, cc.n, op, m, r, G); break;
+                case 4: op_dense<4>(dst, cc.n, op, m, r, G); break;
+                case 5: op_dense<5>(dst, cc.n, op, m, r, G); break;
+                default: op_dense<6>(dst, cc.n, op, m, r, G); break;
                 }
                 break;
             }
             case OP_DIAG:
-                op_diag(dst, cc.n, op, pool + op.mat);
+                op_diag(dst, cc.n, op, pool + op.mat, r, G);
                 break;
             case OP_FFT_LDS:
                 op_fft_lds(dst, cc.n, op);
                 break;
             case OP_FFT_PASS: {
                 const PassArgs &pa = passes[op.pass];
-                for (uint64_t t = 0; t < pa.tiles; ++t)
+                for (uint64_t t = r; t < pa.tiles; t += G)
                     fftdev::fft_tile<float, kBT>(src, dst, pa, t, lds_raw);
                 break;
             }
@@ -320,13 +380,14 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2
                         if (e < (1u << cc.n)) lst[e] = v[q];
                     }
                 } else {
-                    for (uint32_t i = threadIdx.x; i < (1u << cc.n); i += kBT) dst[i] = src[perm_src(i, op, s_tbl)];
+                    for (uint32_t i = r * kBT + threadIdx.x; i < (1u << cc.n); i += G * kBT)
+                        dst[i] = src[perm_src(i, op, s_tbl)];
                 }
                 break;
             }
             case OP_NORM: {
                 double s = 0.0, z = 0.0;
-                for (uint32_t i = threadIdx.x; i < (1u << cc.n); i += kBT) {
+                for (uint32_t i = r * kBT + threadIdx.x; i < (1u << cc.n); i += G * kBT) {
                     const float2 a = src[i];
                     const double p = double(a.x) * a.x + double(a.y) * a.y;
                     s += p;
@@ -347,22 +408,38 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2
                         ts += s_red[0][w];
                         tz += s_red[1][w];
                     }
-                    norms[order[qi]] = ts;
-                    z0[order[qi]] = tz;
+                    partials[cc.p0 + int(r)] = double2{ts, tz};
+                }
+                if (G > 1) gang_sync(bars + tk.circ, G, epoch, err);
+                if (lead) {
+                    // members summed in a fixed order: the result does not
+                    // depend on which workgroup finished first
+                    double ts = 0.0, tz = 0.0;
+                    for (uint32_t m = 0; m < G; ++m) {
+                        const double2 pm = partials[cc.p0 + int(m)];
+                        ts += pm.x;
+                        tz += pm.y;
+                    }
+                    norms[tk.circ] = ts;
+                    z0[tk.circ] = tz;
                 }
                 break;
             }
             default:
                 break;
             }
-            __syncthreads();
+            if (G > 1 && o + 1 < cc.op1)
+                gang_sync(bars + tk.circ, G, epoch, err);
+            else
+                __syncthreads();
         }
-        if (threadIdx.x == 0 && cur_seg >= 0) seg_ticks[cur_seg] = wall_clock64() - t_seg;
+        if (lead && cur_seg >= 0) seg_ticks[cur_seg] = wall_clock64() - t_seg;
         if (in_lds) {
             float2 *out = buf_a;
             for (uint32_t i = threadIdx.x; i < (1u << cc.n); i += kBT) out[i] = lst[i];
         }
         __syncthreads();
+        if (threadIdx.x == 0) trace[qi] = ulonglong2{t_ticket, (wall_clock64() << 12) | (blockIdx.x & 4095u)};
     }
 }
 
@@ -412,7 +489,12 @@ struct qs_batch_t {
     size_t pool_floats = 0, pool_cap = 0;
     BOp *d_ops = nullptr;
     BCirc *d_circ = nullptr;
-    int *d_order = nullptr;
+    Ticket *d_tickets = nullptr;
+    double2 *d_partials = nullptr;
+    ulonglong2 *d_trace = nullptr;   // per ticket: start tick, end tick << 12 | workgroup
+    std::vector<Ticket> tickets;     // host copy of the queue
+    int n_tickets = 0;
+    int grid = 0;                 // co-resident workgroups of the persistent launch
     PassArgs *d_passes = nullptr;
     unsigned *d_counter = nullptr;
     uint64_t *d_ticks = nullptr;
@@ -506,15 +588,54 @@ void seg_features(qs_batch_t *b, SegInfo &s, double batch_bytes)
     b->list_stats[skey] = std::vector<float>(f, f + QS_N_FEATURES);
 }
 
+// Workgroups of k_batch that fit on the device at once (the persistent grid;
+// also the bound a gang must stay under so that all its members run).
+int resident_grid(int &grid)
+{
+    static int cached = 0;
+    if (!cached) {
+        QS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(kLds)));
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        QS_HIP(hipGetDevice(&dev));
+        QS_HIP(hipGetDeviceProperties(&prop, dev));
+        QS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_batch), kBT, kLds));
+        if (per_cu < 1) return fail(QS_EDEVICE, "the batch kernel does not fit on a compute unit");
+        cached = std::min(per_cu, 2) * prop.multiProcessorCount;
+    }
+    grid = cached;
+    return QS_OK;
+}
+
+// Gang size of an HBM circuit: the smallest power of two that brings its
+// time per member under a quarter of the average work per workgroup
+// (`share`), so that gangs remove the tail of a batch with few large
+// circuits and stay small (few barriers) when many circuits already keep
+// every workgroup busy. At least 2^12 amplitudes per member, at most a
+// quarter of the co-resident workgroups.
+int gang_size(int n, double cost, double share, int grid)
+{
+    if (n <= kNS) return 1;
+    const double want = 4.0 * cost / std::max(share, 1.0);
+    int g = 1;
+    while (g < want && g < (1 << std::min(n - 12, 20))) g <<= 1;
+    return std::max(1, std::min(g, grid / 4));
+}
+
 int free_plan(qs_batch_t *b)
 {
     if (b->d_ops) (void)hipFree(b->d_ops);
     if (b->d_circ) (void)hipFree(b->d_circ);
-    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_tickets) (void)hipFree(b->d_tickets);
+    if (b->d_partials) (void)hipFree(b->d_partials);
+    if (b->d_trace) (void)hipFree(b->d_trace);
     if (b->d_passes) (void)hipFree(b->d_passes);
     b->d_ops = nullptr;
     b->d_circ = nullptr;
-    b->d_order = nullptr;
+    b->d_tickets = nullptr;
+    b->d_partials = nullptr;
+    b->d_trace = nullptr;
     b->d_passes = nullptr;
     b->planned = false;
     return QS_OK;
@@ -746,7 +867,7 @@ int qs_batch_create(int n_circuits, const qs_batch_circuit *circuits, void *hip_
     hipError_t e;
     if ((e = hipMalloc(reinterpret_cast<void **>(&b->A), sizeof(float2) * b->a_elems)) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&b->B), sizeof(float2) * std::max<size_t>(b->b_elems, 32))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void **>(&b->d_counter), 64)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&b->d_counter), sizeof(unsigned) * (2 + size_t(n_circuits)))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&b->d_ticks), sizeof(uint64_t) * std::max<size_t>(b->segs.size(), 1))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&b->d_norm), sizeof(double) * size_t(n_circuits))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&b->d_z0), sizeof(double) * size_t(n_circuits))) != hipSuccess) {
@@ -903,19 +1024,40 @@ int qs_batch_set_plan(qs_batch b, const int *options)
     // seg -2 (final norm) must not overwrite a segment time: map to -1
     for (auto &op : ops)
         if (op.seg < 0) op.seg = -1;
+    // gangs, tickets (largest time per member first), norm partial slots
+    int grid = 0;
+    if (int rc = resident_grid(grid)) return rc;
+    int p0 = 0;
+    const double share = std::accumulate(cost.begin(), cost.end(), 0.0) / grid;
+    for (int c = 0; c < b->n_circ; ++c) {
+        circ[size_t(c)].gang = gang_size(b->cn[size_t(c)], cost[size_t(c)], share, grid);
+        circ[size_t(c)].p0 = p0;
+        p0 += circ[size_t(c)].gang;
+    }
     std::vector<int> order(size_t(b->n_circ));
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[size_t(x)] > cost[size_t(y)]; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return cost[size_t(x)] / circ[size_t(x)].gang > cost[size_t(y)] / circ[size_t(y)].gang;
+    });
+    std::vector<Ticket> tickets;
+    tickets.reserve(size_t(p0));
+    for (int c : order)
+        for (int m = 0; m < circ[size_t(c)].gang; ++m) tickets.push_back(Ticket{c, m});
     free_plan(b);
     hipError_t e;
     if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_ops), sizeof(BOp) * ops.size())) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&b->d_circ), sizeof(BCirc) * circ.size())) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void **>(&b->d_order), sizeof(int) * order.size())) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&b->d_tickets), sizeof(Ticket) * tickets.size())) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&b->d_partials), sizeof(double2) * tickets.size())) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&b->d_trace), sizeof(ulonglong2) * tickets.size())) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&b->d_passes), sizeof(PassArgs) * std::max<size_t>(passes.size(), 1))) != hipSuccess)
         return hip_fail(e, "hipMalloc(batch plan)");
+    b->n_tickets = int(tickets.size());
+    b->tickets = tickets;
+    b->grid = grid;
     QS_HIP(hipMemcpyAsync(b->d_ops, ops.data(), sizeof(BOp) * ops.size(), hipMemcpyHostToDevice, b->stream));
     QS_HIP(hipMemcpyAsync(b->d_circ, circ.data(), sizeof(BCirc) * circ.size(), hipMemcpyHostToDevice, b->stream));
-    QS_HIP(hipMemcpyAsync(b->d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, b->stream));
+    QS_HIP(hipMemcpyAsync(b->d_tickets, tickets.data(), sizeof(Ticket) * tickets.size(), hipMemcpyHostToDevice, b->stream));
     if (!passes.empty())
         QS_HIP(hipMemcpyAsync(b->d_passes, passes.data(), sizeof(PassArgs) * passes.size(), hipMemcpyHostToDevice, b->stream));
     QS_HIP(hipStreamSynchronize(b->stream));
@@ -928,26 +1070,18 @@ int qs_batch_run(qs_batch b, double *wall_ms, double *seg_us, double *norms, dou
     clear_error();
     if (!b) return fail(QS_EINVAL, "NULL batch");
     if (!b->planned) return fail(QS_EINVAL, "batch has no plan (qs_batch_set_plan)");
-    static bool attr = false;
-    if (!attr) {
-        QS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(kLds)));
-        attr = true;
-    }
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    }
+    // the grid never exceeds what is co-resident (each gang fits in it)
+    const int grid = std::min(b->n_tickets, b->grid);
+    const int n_cnt = 2 + b->n_circ;
     hipEvent_t e0, e1;
     QS_HIP(hipEventCreate(&e0));
     QS_HIP(hipEventCreate(&e1));
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, b->stream, b->d_counter);
+    hipLaunchKernelGGL(k_reset, dim3(std::min((n_cnt + 255) / 256, 1024)), dim3(256), 0, b->stream, b->d_counter, n_cnt);
     QS_HIP(hipGetLastError());
     QS_HIP(hipEventRecord(e0, b->stream));
-    const int grid = std::min(b->n_circ, 2 * cus);
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), kLds, b->stream, b->A, b->B, b->d_circ, b->d_order,
-                       b->n_circ, b->d_ops, b->pool, b->d_passes, b->d_counter, b->d_ticks, b->d_norm, b->d_z0);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), kLds, b->stream, b->A, b->B, b->d_circ, b->d_tickets,
+                       b->n_tickets, b->d_ops, b->pool, b->d_passes, b->d_counter, b->d_ticks, b->d_partials,
+                       b->d_norm, b->d_z0, b->d_trace);
     QS_HIP(hipGetLastError());
     QS_HIP(hipEventRecord(e1, b->stream));
     QS_HIP(hipEventSynchronize(e1));
@@ -955,6 +1089,9 @@ int qs_batch_run(qs_batch b, double *wall_ms, double *seg_us, double *norms, dou
     QS_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    unsigned flags[2] = {0, 0};
+    QS_HIP(hipMemcpy(flags, b->d_counter, sizeof flags, hipMemcpyDeviceToHost));
+    if (flags[1]) return fail(QS_EDEVICE, "a gang barrier of the batch kernel timed out; results are invalid");
     if (wall_ms) *wall_ms = double(ms);
     if (seg_us) {
         std::vector<uint64_t> t(b->segs.size());
@@ -963,6 +1100,32 @@ int qs_batch_run(qs_batch b, double *wall_ms, double *seg_us, double *norms, dou
     }
     if (norms) QS_HIP(hipMemcpy(norms, b->d_norm, sizeof(double) * size_t(b->n_circ), hipMemcpyDeviceToHost));
     if (z0) QS_HIP(hipMemcpy(z0, b->d_z0, sizeof(double) * size_t(b->n_circ), hipMemcpyDeviceToHost));
+    return QS_OK;
+}
+
+int qs_batch_trace(qs_batch b, int capacity, int *n_tickets, double *start_us, double *end_us, int *circuit,
+                   int *member, int *workgroup)
+{
+    clear_error();
+    if (!b || !n_tickets) return fail(QS_EINVAL, "NULL argument");
+    if (!b->planned) return fail(QS_EINVAL, "batch has no plan (qs_batch_set_plan)");
+    *n_tickets = b->n_tickets;
+    const int cnt = std::min(std::max(capacity, 0), b->n_tickets);
+    if (cnt == 0) return QS_OK;
+    std::vector<ulonglong2> t(size_t(b->n_tickets));
+    QS_HIP(hipStreamSynchronize(b->stream));
+    QS_HIP(hipMemcpy(t.data(), b->d_trace, sizeof(ulonglong2) * t.size(), hipMemcpyDeviceToHost));
+    uint64_t t0 = ~0ull;
+    for (const auto &x : t) t0 = std::min<uint64_t>(t0, x.x);
+    const double us = 1000.0 / b->clock_khz;
+    for (int i = 0; i < cnt; ++i) {
+        const ulonglong2 &x = t[size_t(i)];
+        if (start_us) start_us[i] = double(x.x - t0) * us;
+        if (end_us) end_us[i] = double((x.y >> 12) - t0) * us;
+        if (workgroup) workgroup[i] = int(x.y & 4095u);
+        if (circuit) circuit[i] = b->tickets[size_t(i)].circ;
+        if (member) member[i] = b->tickets[size_t(i)].member;
+    }
     return QS_OK;
 }
 

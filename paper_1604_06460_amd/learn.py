@@ -30,19 +30,30 @@ def _say(log, msg):
         log(msg)
 
 
-def collect(batch, runs, seed, with_policies=True, log=None):
-    """Run `batch` under `runs` random plans (plus the plain policies) and
-    return (X, T, mask): features, mean natural-log device microseconds per
-    option, and which options were measured."""
+def explore_options(base, kinds, rng, frac):
+    """`base` with a random fraction `frac` of its segments given a random
+    valid option: plans near a sensible one, so that the timed segments run
+    among neighbours like those of the plans that will be chosen later."""
+    o = np.array(base, dtype=np.int32, copy=True)
+    flip = rng.random(o.size) < frac
+    o[flip] = random_options(kinds[flip], rng)
+    return o
+
+
+def collect(batch, runs, seed, with_policies=True, frac=0.35, log=None):
+    """Run `batch` under the plain policies (if `with_policies`) and `runs`
+    perturbations of them, and return (X, T, mask): features, mean
+    natural-log device microseconds per option, and which options were
+    measured."""
     rng = np.random.default_rng(seed)
     kinds, _, _ = batch.segment_info()
     X = batch.features()
     n = batch.n_segments
     s = np.zeros((n, 4))
     c = np.zeros((n, 4))
-    plans = [random_options(kinds, rng) for _ in range(runs)]
-    if with_policies:
-        plans += [Q.choose(batch, p) for p in PLAIN.values()]
+    bases = [Q.choose(batch, p) for p in PLAIN.values()]
+    plans = list(bases) if with_policies else []
+    plans += [explore_options(bases[i % len(bases)], kinds, rng, frac) for i in range(runs)]
     idx = np.arange(n)
     for pi, opts in enumerate(plans):
         batch.set_plan(opts)
@@ -57,10 +68,15 @@ def collect(batch, runs, seed, with_policies=True, log=None):
 
 
 def fit(X, T, mask, epochs=80, batch=256, lr=2e-3, seed=0):
-    """Standardise the features and train the model with Adam."""
-    mean = X.mean(0)
-    std = X.std(0)
-    inv = 1.0 / np.where(std > 1e-6, std, 1.0)
+    """Standardise the features and train the model with Adam. A feature
+    that does not vary over the training rows (up to float rounding, e.g.
+    the batch-level size on a single training batch) is switched off: the
+    model cannot learn its effect, and scaling rounding noise up would turn
+    a different value at inference into a huge input."""
+    X64 = X.astype(np.float64)
+    mean = X64.mean(0)
+    std = X64.std(0)
+    inv = np.where(std > 1e-4 * np.maximum(1.0, np.abs(mean)), 1.0 / np.maximum(std, 1e-30), 0.0)
     m = Q.Mlp(seed=seed)
     m.set_norm(mean, inv)
     loss = m.train(X, T, mask, epochs, batch, lr, seed)

@@ -100,6 +100,7 @@ _sig("qs_batch_features", [_P, _P])
 _sig("qs_batch_set_plan", [_P, _P])
 _sig("qs_batch_run", [_P, C.POINTER(_D), _P, _P, _P])
 _sig("qs_batch_get_state", [_P, _I, _P])
+_sig("qs_batch_trace", [_P, _I, C.POINTER(_I), _P, _P, _P, _P, _P])
 _sig("qs_batch_free", [_P])
 _sig("qs_mlp_create", [_P, _U64, _P, C.POINTER(_P)])
 _sig("qs_mlp_get_params", [_P, _P])
@@ -470,6 +471,18 @@ class Batch:
         z0 = np.zeros(self.n_circuits, dtype=np.float64)
         _chk(_L.qs_batch_run(self._h, C.byref(ms), _ptr(seg), _ptr(norms), _ptr(z0)))
         return ms.value, seg, norms, z0
+
+    def trace(self):
+        """Schedule of the last run, one row per ticket in queue order:
+        dict of start_us, end_us, circuit, member, workgroup arrays."""
+        cnt = _I()
+        _chk(_L.qs_batch_trace(self._h, 0, C.byref(cnt), None, None, None, None, None))
+        n = cnt.value
+        out = {"start_us": np.zeros(n), "end_us": np.zeros(n), "circuit": np.zeros(n, dtype=np.int32),
+               "member": np.zeros(n, dtype=np.int32), "workgroup": np.zeros(n, dtype=np.int32)}
+        _chk(_L.qs_batch_trace(self._h, n, C.byref(cnt), _ptr(out["start_us"]), _ptr(out["end_us"]),
+                               _ptr(out["circuit"]), _ptr(out["member"]), _ptr(out["workgroup"])))
+        return out
 
     def state(self, c):
         out = np.empty(1 << self.ns[c], dtype=np.complex64)

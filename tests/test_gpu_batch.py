@@ -111,3 +111,34 @@ def test_batch_features_shape_and_content(Q, S, small_batch):
     assert np.array_equal(f[:, 3:6].sum(1), np.ones(len(kinds), dtype=np.float32))
     assert (f[:, 17] >= f[:, 18]).all() and (f[:, 18] >= f[:, 19]).all()   # fewer blocks at larger k
     b.free()
+
+
+def test_gangs_on_large_circuits_match_oracle(Q, O, S):
+    """20-22 qubit circuits swept by gangs of 64-128 workgroups (one gang may
+    be the whole grid when the batch is this small)."""
+    circuits = S.batch_mix(3, 79, n_range=(20, 22), d_range=(3, 5), p_qft=0.3, p_modmul=0.3)
+    b = Q.Batch(circuits)
+    kinds, _, _ = b.segment_info()
+    b.set_plan(_options(kinds, "random", np.random.default_rng(9)))
+    _, _, norms, z0 = b.run()
+    for c, circ in enumerate(circuits):
+        ref = oracle_circuit(O, S, circ)
+        got = b.state(c).astype(np.complex128)
+        assert np.abs(got - ref).max() < 1e-5, (c, circ.n)
+        assert abs(norms[c] - 1) < 1e-5
+    b.free()
+
+
+def test_batch_runs_are_bit_reproducible(Q, S, small_batch):
+    """Gang members split every op over disjoint amplitudes and the norm
+    partials are summed in member order, so two runs agree bit for bit."""
+    b = Q.Batch(small_batch)
+    kinds, _, _ = b.segment_info()
+    b.set_plan(_options(kinds, 1))
+    _, _, n1, z1 = b.run()
+    s1 = [b.state(c) for c in range(len(small_batch))]
+    _, _, n2, z2 = b.run()
+    assert np.array_equal(n1, n2) and np.array_equal(z1, z2)
+    for c in range(len(small_batch)):
+        assert np.array_equal(b.state(c).view(np.uint8), s1[c].view(np.uint8)), c
+    b.free()

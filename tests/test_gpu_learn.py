@@ -81,10 +81,10 @@ def test_training_fits_a_smooth_target(Q):
 def test_learned_plan_choice_on_held_out_batch(Q, O, S):
     """Train on timings of one batch, choose plans for a disjoint batch:
     the learned plans give the oracle's states and run no slower (within
-    measurement noise) than the best plain policy."""
+    5 %, the run-to-run spread of one launch) than the best plain policy."""
     from paper_1604_06460_amd import learn
     train = Q.Batch(S.batch_mix(160, S.SEED_BASE * 1000 + 500000, n_range=(10, 20), d_range=(6, 20)))
-    X, T, mask = learn.collect(train, runs=4, seed=1)
+    X, T, mask = learn.collect(train, runs=8, seed=1)
     train.free()
     model, loss = learn.fit(X, T, mask, epochs=60)
     assert np.isfinite(loss)
@@ -93,7 +93,7 @@ def test_learned_plan_choice_on_held_out_batch(Q, O, S):
     res, plans = learn.wall_times(ev, model, repeats=3)
     ratio, best = learn.learned_vs_plain(res)
     print("wall ms per policy:", res, "learned / best plain (%s) = %.3f" % (best, ratio))
-    assert ratio < 1.15
+    assert ratio < 1.05
     # results are exact under the learned plan
     ev.set_plan(plans["learned"])
     ev.run()
