@@ -384,6 +384,50 @@ enum qs_policy { QS_POLICY_HEURISTIC = 0, QS_POLICY_LEARNED = 1, QS_POLICY_FIXED
                  QS_POLICY_FIXED_K4 = 3, QS_POLICY_FIXED_K6 = 4 };
 int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
 
+/* ---------------------------------------------------------------------- */
+/* Launch-parameter table (filled by an autotuner, read by the dispatchers) */
+/* ---------------------------------------------------------------------- */
+
+/* Parameters. Every value is an int; 0 restores the built-in default.
+ *   QS_TUNE_SWEEP_PATH (dtype, k, class, n bucket): kernel for an
+ *     uncontrolled dense k-qubit block: 1 thread per group (registers),
+ *     2 wave tiles staged through LDS (needs n >= 6 + k; k <= 5 for
+ *     complex128), 3 FP32 matrix cores (complex64, k = 6, n >= 12). A path
+ *     that does not apply to a block falls back to the default rule (LDS
+ *     below the line size, matrix cores for complex64 k = 6, registers
+ *     otherwise). Every path computes the same products; only the
+ *     summation order of the FP32/FP64 dot products may differ.
+ *   QS_TUNE_SWEEP_WG_PER_CU (dtype, k, class, n bucket): cap of the dense
+ *     sweep grid in workgroups per compute unit (grid-stride beyond it).
+ *   QS_TUNE_FFT_DIGIT (dtype, -, -, n bucket): largest FFT digit (bits per
+ *     pass), 2..10.
+ *   QS_TUNE_FFT_LDS_KB (dtype, -, -, n bucket): LDS tile budget of an FFT
+ *     pass, 8..64 KiB.
+ *   QS_TUNE_MFMA_WG_PER_CU (complex64, k = 6, -, n bucket): persistent grid
+ *     of the matrix-core sweep in workgroups per compute unit, 1..16.
+ *   QS_TUNE_BATCH_GANG_SHARE (-, -, -, -): a batch circuit's gang is sized
+ *     so its time per member is below 1/value of the average work per
+ *     workgroup, 1..256.
+ *   QS_TUNE_BATCH_BARRIER_AMPS (-, -, -, -): cost of a gang barrier, in
+ *     amplitude-op units, used to order the batch queue.
+ * Index dimensions: dtype QS_C64/QS_C128; k 0..QS_MAX_K; class
+ * QS_TCLS_* of the lowest target; n bucket 0 (n < 22), 1 (22..27),
+ * 2 (n >= 28). Dimensions a parameter ignores are read at index 0.
+ * qs_tune_set accepts -1 in any index as "all". The table is process-wide
+ * and not synchronised: set it before launching work from other threads. */
+enum qs_tune_param { QS_TUNE_SWEEP_PATH = 0, QS_TUNE_SWEEP_WG_PER_CU = 1, QS_TUNE_FFT_DIGIT = 2,
+                     QS_TUNE_FFT_LDS_KB = 3, QS_TUNE_MFMA_WG_PER_CU = 4,
+                     QS_TUNE_BATCH_GANG_SHARE = 5, QS_TUNE_BATCH_BARRIER_AMPS = 6,
+                     QS_TUNE_COUNT = 7 };
+/* Target classes: lowest target inside a 128-byte line, inside a wave's
+ * 64 consecutive amplitudes, or above bit 5. */
+enum qs_tune_class { QS_TCLS_SUBLINE = 0, QS_TCLS_SUBWAVE = 1, QS_TCLS_HIGH = 2 };
+int qs_tune_set(int param, int dtype, int k, int cls, int nbucket, int value);
+int qs_tune_get(int param, int dtype, int k, int cls, int nbucket, int *value);
+int qs_tune_reset(void);
+/* The class and n bucket the dispatchers use for a block. */
+int qs_tune_classify(int dtype, int n_qubits, int k, const int *targets, int *cls, int *nbucket);
+
 #ifdef __cplusplus
 }
 #endif

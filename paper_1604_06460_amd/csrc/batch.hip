@@ -11,8 +11,8 @@
 // per ticket (largest first). Circuits of at most 13 qubits (64 KiB of
 // complex64) have one ticket: one workgroup keeps the state in LDS from the
 // first op to the last and writes it to HBM once. A larger circuit is swept
-// in HBM by a gang of G workgroups (G grows with 2^n), one ticket per
-// member: each op is split over the members, and the members meet at a
+// in HBM by a gang of G workgroups (G sized from the plan's cost estimate),
+// one ticket per member: each op is split over the members, which meet at a
 // cross-workgroup barrier (a monotonic arrival counter per circuit) between
 // ops. A gang's tickets are consecutive in the queue, so only the most
 // recently opened gang can be waiting for members, and any workgroup that
@@ -609,7 +609,7 @@ int resident_grid(int &grid)
 }
 
 // Gang size of an HBM circuit: the smallest power of two that brings its
-// time per member under a quarter of the average work per workgroup
+// time per member under a quarter (tunable) of the average work per workgroup
 // (`share`), so that gangs remove the tail of a batch with few large
 // circuits and stay small (few barriers) when many circuits already keep
 // every workgroup busy. At least 2^12 amplitudes per member, at most a
@@ -617,7 +617,8 @@ int resident_grid(int &grid)
 int gang_size(int n, double cost, double share, int grid)
 {
     if (n <= kNS) return 1;
-    const double want = 4.0 * cost / std::max(share, 1.0);
+    const int tuned = tune_value(QS_TUNE_BATCH_GANG_SHARE, QS_C64, 0, 0, 0);
+    const double want = double(tuned ? tuned : 4) * cost / std::max(share, 1.0);
     int g = 1;
     while (g < want && g < (1 << std::min(n - 12, 20))) g <<= 1;
     return std::max(1, std::min(g, grid / 4));
@@ -1034,11 +1035,20 @@ int qs_batch_set_plan(qs_batch b, const int *options)
         circ[size_t(c)].p0 = p0;
         p0 += circ[size_t(c)].gang;
     }
+    // time per ticket, in amplitude-op units: the member's share of the
+    // work plus, for a gang, one barrier per op (about as long as sweeping
+    // kBarrierAmps amplitudes)
+    const int tuned_bar = tune_value(QS_TUNE_BATCH_BARRIER_AMPS, QS_C64, 0, 0, 0);
+    const double kBarrierAmps = tuned_bar ? double(tuned_bar) : 4096.0;
+    std::vector<double> per_ticket(size_t(b->n_circ));
+    for (int c = 0; c < b->n_circ; ++c) {
+        const BCirc &C = circ[size_t(c)];
+        per_ticket[size_t(c)] = cost[size_t(c)] / C.gang + (C.gang > 1 ? kBarrierAmps * (C.op1 - C.op0) : 0.0);
+    }
     std::vector<int> order(size_t(b->n_circ));
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return cost[size_t(x)] / circ[size_t(x)].gang > cost[size_t(y)] / circ[size_t(y)].gang;
-    });
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return per_ticket[size_t(x)] > per_ticket[size_t(y)]; });
     std::vector<Ticket> tickets;
     tickets.reserve(size_t(p0));
     for (int c : order)

@@ -51,19 +51,19 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const typename V2<R>::T *__rest
 
 // Pass shape: widest digit and LDS bytes per workgroup tile. Narrower digits
 // mean more passes but longer contiguous runs per global access (the tile
-// holds LDS/(2^r * amplitude) columns). Overridable for tuning through
-// QS_FFT_DIGIT / QS_FFT_LDS_KB.
+// holds LDS/(2^r * amplitude) columns). Both come from the tuning table
+// (per dtype and n bucket), else the widest digit and the full budget.
 struct FftShape {
     int digit = kRmax;
     size_t lds = kLdsBytes;
 };
 
-FftShape fft_shape()
+FftShape fft_shape(int dtype, int n)
 {
     FftShape s;
-    if (const char *e = getenv("QS_FFT_DIGIT")) s.digit = std::max(1, std::min(kRmax, atoi(e)));
-    if (const char *e = getenv("QS_FFT_LDS_KB"))
-        s.lds = size_t(std::max(4, std::min(64, atoi(e)))) * 1024;
+    const int nb = tune_nbucket(n);
+    if (const int dg = tune_value(QS_TUNE_FFT_DIGIT, dtype, 0, 0, nb)) s.digit = std::min(kRmax, dg);
+    if (const int kb = tune_value(QS_TUNE_FFT_LDS_KB, dtype, 0, 0, nb)) s.lds = std::min(kLdsBytes, size_t(kb) * 1024);
     return s;
 }
 
@@ -71,7 +71,7 @@ template <typename R>
 int run_fft(qs_state *h, int q_lo, int m, int inverse)
 {
     using C2 = typename V2<R>::T;
-    const FftShape shape = fft_shape();
+    const FftShape shape = fft_shape(h->dtype, h->n);
     std::vector<PassArgs> passes;
     if (int rc = plan_passes(h->n, q_lo, m, inverse, shape.digit, shape.lds, sizeof(C2), passes)) return rc;
     const int P = int(passes.size());

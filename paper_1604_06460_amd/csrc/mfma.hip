@@ -193,12 +193,9 @@ int launch_t(qs_state *h, const GateDesc &d, const float *dmat)
     for (int t = 0; t < 32; ++t) ta.offc_even[t] = offc(2 * t);
     ta.bit0_pos = compact(d.targets[0]);
     const IT n_tiles = IT(h->dim() >> 12);
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    }
-    const uint64_t grid = std::min<uint64_t>(uint64_t(n_tiles), uint64_t(cus) * 4);
+    // persistent grid: tuned workgroups per CU (default 4)
+    const int per_cu = tune_value(QS_TUNE_MFMA_WG_PER_CU, QS_C64, 6, 0, tune_nbucket(h->n));
+    const uint64_t grid = std::min<uint64_t>(uint64_t(n_tiles), uint64_t(device_cus()) * uint64_t(per_cu ? per_cu : 4));
     hipLaunchKernelGGL((k_dense_mfma6<IT>), dim3(unsigned(grid)), dim3(64 * kWaves), 0, h->stream,
                        static_cast<float2 *>(h->psi), dmat, n_tiles, ta);
     QS_HIP(hipGetLastError());
@@ -209,8 +206,7 @@ int launch_t(qs_state *h, const GateDesc &d, const float *dmat)
 
 bool mfma_applicable(const qs_state *h, const GateDesc &d)
 {
-    return h->dtype == QS_C64 && d.k == 6 && d.ctrl_mask == 0 && h->n >= 12 &&
-           !getenv("QS_NO_MFMA");
+    return h->dtype == QS_C64 && d.k == 6 && d.ctrl_mask == 0 && h->n >= 12;
 }
 
 int launch_dense_mfma(qs_state *h, const GateDesc &d, const void *dmat)

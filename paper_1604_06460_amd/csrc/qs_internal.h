@@ -135,6 +135,12 @@ int emulate_qft(qs_state *h, int q_lo, int m, int inverse);
 int measure(qs_state *h, int m, const int *qubits, int shots, const double *u,
             uint64_t *outcomes, double *probs, int collapse);
 
+// Launch-parameter table (tune.cpp): 0 = built-in default
+int tune_value(int param, int dtype, int k, int cls, int nbucket);
+int tune_class(int min_target, int dtype);
+int tune_nbucket(int n);
+int device_cus();
+
 // Device buffers attached to a handle
 int ensure_partials(qs_state *h, size_t count);
 int ensure_host_out(qs_state *h, size_t bytes);

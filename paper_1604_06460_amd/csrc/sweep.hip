@@ -369,17 +369,26 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
     const IT n_groups = IT(h->dim() >> np);
     C2 *psi = static_cast<C2 *>(h->psi);
     const R *m = static_cast<const R *>(dmat);
-    // 6-qubit blocks on complex64 states: batched GEMM on the matrix cores
-    if constexpr (sizeof(R) == 4 && K == 6) {
-        if (mfma_applicable(h, d)) return launch_dense_mfma(h, d, dmat);
-    }
-    // targets inside a 128-byte line: stage the tile through LDS
-    constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
-    constexpr bool lds_capable = (sizeof(R) == 8) ? (K <= 5) : (K <= 6);
     int mint = 64;
     for (int i = 0; i < K; ++i) mint = std::min(mint, d.targets[i]);
+    // tuned choices for this (dtype, k, target class, n bucket); 0 = default
+    const int cls = tune_class(mint, h->dtype), nb = tune_nbucket(h->n);
+    const int path = tune_value(QS_TUNE_SWEEP_PATH, h->dtype, K, cls, nb);
+    const int wg_per_cu = tune_value(QS_TUNE_SWEEP_WG_PER_CU, h->dtype, K, cls, nb);
+    auto capped = [&](uint64_t g) {
+        if (wg_per_cu) g = std::min<uint64_t>(g, uint64_t(wg_per_cu) * uint64_t(device_cus()));
+        return unsigned(std::max<uint64_t>(g, 1));
+    };
+    // 6-qubit blocks on complex64 states: batched GEMM on the matrix cores
+    if constexpr (sizeof(R) == 4 && K == 6) {
+        if ((path == 0 || path == 3) && mfma_applicable(h, d)) return launch_dense_mfma(h, d, dmat);
+    }
+    // by default, targets inside a 128-byte line stage the tile through LDS
+    constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
+    constexpr bool lds_capable = (sizeof(R) == 8) ? (K <= 5) : (K <= 6);
     if constexpr (lds_capable) {
-        if (d.ctrl_mask == 0 && mint < kLineBits && h->n >= 6 + K && !getenv("QS_NO_LDS_SWEEP")) {
+        const bool lds_ok = d.ctrl_mask == 0 && h->n >= 6 + K;
+        if (lds_ok && (path == 2 || (path != 1 && mint < kLineBits))) {
             uint64_t tmask = 0;
             for (int i = 0; i < K; ++i) tmask |= 1ull << d.targets[i];
             int klo = 0;
@@ -415,8 +424,8 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
             FixArgs ft;
             if (int rc = make_fix(P.data(), int(P.size()), 0, ft)) return rc;
             const IT n_tiles = IT(h->dim() >> (6 + K));
-            const uint64_t grid = std::min<uint64_t>(uint64_t(n_tiles), 1ull << 22);
-            hipLaunchKernelGGL((k_dense_lds<R, K, IT>), dim3(unsigned(grid)), dim3(64), 0, h->stream, psi,
+            const unsigned grid = capped(std::min<uint64_t>(uint64_t(n_tiles), 1ull << 22));
+            hipLaunchKernelGGL((k_dense_lds<R, K, IT>), dim3(grid), dim3(64), 0, h->stream, psi,
                                m, n_tiles, ft, offl, la);
             QS_HIP(hipGetLastError());
             return QS_OK;
@@ -424,10 +433,10 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
     }
     constexpr bool split = (sizeof(R) == 8 && K >= 6);
     if constexpr (split) {
-        hipLaunchKernelGGL((k_dense_split<R, K, 8, IT>), dim3(grid_for(uint64_t(n_groups) * (D / 8))),
+        hipLaunchKernelGGL((k_dense_split<R, K, 8, IT>), dim3(capped(grid_for(uint64_t(n_groups) * (D / 8)))),
                            dim3(kBlock), 0, h->stream, psi, m, n_groups, fx, off);
     } else {
-        hipLaunchKernelGGL((k_dense<R, K, IT>), dim3(grid_for(n_groups)), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_dense<R, K, IT>), dim3(capped(grid_for(n_groups))), dim3(kBlock), 0,
                            h->stream, psi, m, n_groups, fx, off);
     }
     QS_HIP(hipGetLastError());

@@ -499,3 +499,58 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Launch-parameter table
+# ---------------------------------------------------------------------------
+_sig("qs_tune_set", [_I, _I, _I, _I, _I, _I])
+_sig("qs_tune_get", [_I, _I, _I, _I, _I, C.POINTER(_I)])
+_sig("qs_tune_reset", [])
+_sig("qs_tune_classify", [_I, _I, _I, _P, C.POINTER(_I), C.POINTER(_I)])
+
+(QS_TUNE_SWEEP_PATH, QS_TUNE_SWEEP_WG_PER_CU, QS_TUNE_FFT_DIGIT, QS_TUNE_FFT_LDS_KB,
+ QS_TUNE_MFMA_WG_PER_CU, QS_TUNE_BATCH_GANG_SHARE, QS_TUNE_BATCH_BARRIER_AMPS) = range(7)
+QS_TCLS_SUBLINE, QS_TCLS_SUBWAVE, QS_TCLS_HIGH = range(3)
+TUNE_PARAMS = {"sweep_path": QS_TUNE_SWEEP_PATH, "sweep_wg_per_cu": QS_TUNE_SWEEP_WG_PER_CU,
+               "fft_digit": QS_TUNE_FFT_DIGIT, "fft_lds_kb": QS_TUNE_FFT_LDS_KB,
+               "mfma_wg_per_cu": QS_TUNE_MFMA_WG_PER_CU, "batch_gang_share": QS_TUNE_BATCH_GANG_SHARE,
+               "batch_barrier_amps": QS_TUNE_BATCH_BARRIER_AMPS}
+TUNED_FILE = os.path.join(_HERE, "tuned", "gfx950.json")
+
+
+def tune_set(param, value, dtype=-1, k=-1, cls=-1, nbucket=-1):
+    _chk(_L.qs_tune_set(int(param), int(dtype), int(k), int(cls), int(nbucket), int(value)))
+
+
+def tune_get(param, dtype=QS_C64, k=0, cls=0, nbucket=0):
+    v = _I()
+    _chk(_L.qs_tune_get(int(param), int(dtype), int(k), int(cls), int(nbucket), C.byref(v)))
+    return v.value
+
+
+def tune_reset():
+    _chk(_L.qs_tune_reset())
+
+
+def tune_classify(dtype, n_qubits, targets):
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    cls, nb = _I(), _I()
+    _chk(_L.qs_tune_classify(int(dtype), int(n_qubits), int(t.size), _ptr(t), C.byref(cls), C.byref(nb)))
+    return cls.value, nb.value
+
+
+def load_tuning(path=TUNED_FILE):
+    """Apply a tuning table written by autotune.save (entries of param name,
+    index fields with -1 for "all", and value). Returns the entry count."""
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    for e in doc["entries"]:
+        tune_set(TUNE_PARAMS[e["param"]], e["value"], e.get("dtype", -1), e.get("k", -1),
+                 e.get("cls", -1), e.get("nbucket", -1))
+    return len(doc["entries"])
+
+
+if os.path.exists(TUNED_FILE):
+    load_tuning(TUNED_FILE)

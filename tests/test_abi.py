@@ -103,3 +103,65 @@ def test_planner_rejects_bad_input(Q, S):
         Q.plan_fusion([S.g1(S.MAT_H, 5)], 4, 2)
     with pytest.raises(Q.QSError):
         Q.plan_fusion([S.g1(S.MAT_H, 0)], 4, 7)
+
+
+# ---------------------------------------------------------------------------
+# Launch-parameter table (host only)
+# ---------------------------------------------------------------------------
+@pytest.fixture
+def clean_tune(Q):
+    Q.tune_reset()
+    yield Q
+    Q.tune_reset()
+    if os.path.exists(Q.TUNED_FILE):
+        Q.load_tuning()
+
+
+def test_tune_table_set_get_and_wildcards(clean_tune):
+    Q = clean_tune
+    assert Q.tune_get(Q.QS_TUNE_SWEEP_PATH, Q.QS_C128, 4, 0, 2) == 0
+    Q.tune_set(Q.QS_TUNE_SWEEP_PATH, 2, Q.QS_C128, 4, Q.QS_TCLS_SUBWAVE, 2)
+    assert Q.tune_get(Q.QS_TUNE_SWEEP_PATH, Q.QS_C128, 4, Q.QS_TCLS_SUBWAVE, 2) == 2
+    assert Q.tune_get(Q.QS_TUNE_SWEEP_PATH, Q.QS_C128, 4, Q.QS_TCLS_SUBWAVE, 1) == 0
+    assert Q.tune_get(Q.QS_TUNE_SWEEP_PATH, Q.QS_C64, 4, Q.QS_TCLS_SUBWAVE, 2) == 0
+    Q.tune_set(Q.QS_TUNE_FFT_DIGIT, 8)                      # every index
+    for dt in (Q.QS_C64, Q.QS_C128):
+        for nb in range(3):
+            assert Q.tune_get(Q.QS_TUNE_FFT_DIGIT, dt, 0, 0, nb) == 8
+    Q.tune_reset()
+    assert Q.tune_get(Q.QS_TUNE_FFT_DIGIT, Q.QS_C64, 0, 0, 0) == 0
+
+
+@pytest.mark.parametrize("args", [
+    (99, -1, -1, -1, -1, 1),                   # unknown parameter
+    (0, 7, -1, -1, -1, 1),                     # dtype
+    (0, -1, 9, -1, -1, 1),                     # k
+    (0, -1, -1, 3, -1, 1),                     # class
+    (0, -1, -1, -1, 3, 1),                     # n bucket
+    (0, -1, -1, -1, -1, 4),                    # path value
+    (2, -1, -1, -1, -1, 11),                   # FFT digit
+    (3, -1, -1, -1, -1, 128),                  # FFT LDS KiB
+    (4, -1, -1, -1, -1, 17),                   # MFMA WG/CU
+])
+def test_tune_set_rejects_bad_arguments(clean_tune, args):
+    Q = clean_tune
+    with pytest.raises(Q.QSError):
+        Q.tune_set(args[0], args[5], *args[1:5])
+    assert Q.tune_get(Q.QS_TUNE_SWEEP_PATH, Q.QS_C64, 1, 0, 0) == 0
+
+
+def test_tune_classes_and_buckets(Q):
+    # lowest target inside a 128-byte line (8 c128 / 16 c64 amplitudes),
+    # inside 64 amplitudes, or above
+    assert Q.tune_classify(Q.QS_C128, 30, [2, 9]) == (Q.QS_TCLS_SUBLINE, 2)
+    assert Q.tune_classify(Q.QS_C128, 30, [3, 9]) == (Q.QS_TCLS_SUBWAVE, 2)
+    assert Q.tune_classify(Q.QS_C64, 25, [3, 9]) == (Q.QS_TCLS_SUBLINE, 1)
+    assert Q.tune_classify(Q.QS_C64, 21, [4, 5]) == (Q.QS_TCLS_SUBWAVE, 0)
+    assert Q.tune_classify(Q.QS_C64, 28, [6, 29]) == (Q.QS_TCLS_HIGH, 2)
+
+
+def test_committed_tuning_table_is_valid(clean_tune):
+    Q = clean_tune
+    if not os.path.exists(Q.TUNED_FILE):
+        pytest.skip("no tuned table committed")
+    assert Q.load_tuning() > 0

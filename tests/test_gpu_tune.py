@@ -1,0 +1,116 @@
+"""Every launch choice the autotuner can make gives the oracle's result:
+each dense sweep path for every width and target class, grid caps that
+force grid-stride loops, every FFT digit/LDS budget, the matrix-core grid,
+and batch gang sizing (states bit-identical across gang settings)."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def Q():
+    from paper_1604_06460_amd import qs
+    qs.tune_reset()
+    yield qs
+    qs.tune_reset()
+    if os.path.exists(qs.TUNED_FILE):
+        qs.load_tuning()
+
+
+def _unitary(k, rng):
+    d = 1 << k
+    z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _targets(cls, k, n, dtype, Q):
+    lb = 3 if dtype == Q.QS_C128 else 4
+    lo = {Q.QS_TCLS_SUBLINE: 0, Q.QS_TCLS_SUBWAVE: lb, Q.QS_TCLS_HIGH: 6}[cls]
+    return sorted([lo] + [n - 1 - 2 * i for i in range(k - 1)])
+
+
+TOL = {0: 2e-5, 1: 1e-12}   # complex64 / complex128, max abs error on a normalised state
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_every_sweep_path_matches_oracle(Q, O, S, dtype, k):
+    n = 16
+    rng = np.random.default_rng(100 + 10 * k + dtype)
+    psi0 = S.normal_state(n, 7 + k)
+    for cls in (Q.QS_TCLS_SUBLINE, Q.QS_TCLS_SUBWAVE, Q.QS_TCLS_HIGH):
+        t = _targets(cls, k, n, dtype, Q)
+        assert Q.tune_classify(dtype, n, t)[0] == cls
+        m = _unitary(k, rng)
+        ref = O.apply_gate(psi0.copy(), t, m)
+        for path in (1, 2, 3):
+            for cap in (0, 1):          # cap 1: one workgroup per CU, grid-stride
+                Q.tune_set(Q.QS_TUNE_SWEEP_PATH, path, dtype, k, cls, -1)
+                Q.tune_set(Q.QS_TUNE_SWEEP_WG_PER_CU, cap, dtype, k, cls, -1)
+                st = Q.State(n, dtype)
+                st.set(psi0)
+                st.apply_gate(t, m)
+                got = st.get().astype(np.complex128)
+                st.free()
+                assert np.abs(got - ref).max() < TOL[dtype], (dtype, k, cls, path, cap)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_every_fft_shape_matches_oracle(Q, O, S, dtype):
+    n = 15
+    psi0 = S.normal_state(n, 21)
+    for q_lo, m in ((0, 15), (2, 11)):
+        ref = O.dft_numpy(psi0, q_lo, m, False)
+        for digit in (2, 4, 7, 10):
+            for kb in (8, 64):
+                Q.tune_set(Q.QS_TUNE_FFT_DIGIT, digit, dtype)
+                Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, kb, dtype)
+                st = Q.State(n, dtype)
+                st.set(psi0)
+                st.emulate_qft(q_lo, m)
+                got = st.get().astype(np.complex128)
+                st.free()
+                assert np.abs(got - ref).max() < 10 * TOL[dtype], (dtype, q_lo, m, digit, kb)
+
+
+def test_mfma_grid_sizes_match_oracle(Q, O, S):
+    n = 18
+    rng = np.random.default_rng(5)
+    psi0 = S.normal_state(n, 3)
+    t = [0, 3, 6, 9, 12, 17]
+    m = _unitary(6, rng)
+    ref = O.apply_gate(psi0.copy(), t, m)
+    for w in (1, 3, 8, 16):
+        Q.tune_set(Q.QS_TUNE_MFMA_WG_PER_CU, w)
+        st = Q.State(n, Q.QS_C64)
+        st.set(psi0)
+        st.apply_gate(t, m)
+        got = st.get().astype(np.complex128)
+        st.free()
+        assert np.abs(got - ref).max() < TOL[0], w
+
+
+def test_batch_gang_settings_give_identical_states(Q, S):
+    circuits = S.batch_mix(24, 91, n_range=(12, 19), d_range=(3, 6), p_qft=0.3, p_modmul=0.3)
+    b = Q.Batch(circuits)
+    opts = Q.choose(b, Q.QS_POLICY_FIXED_K4)
+    ref = None
+    for share, bar in ((1, 1), (4, 4096), (64, 1 << 20), (256, 16)):
+        Q.tune_set(Q.QS_TUNE_BATCH_GANG_SHARE, share)
+        Q.tune_set(Q.QS_TUNE_BATCH_BARRIER_AMPS, bar)
+        b.set_plan(opts)
+        _, _, norms, _ = b.run()
+        states = [b.state(c) for c in range(len(circuits))]
+        tr = b.trace()
+        assert len(tr["circuit"]) >= len(circuits)
+        assert (tr["end_us"] >= tr["start_us"]).all()
+        if ref is None:
+            ref = states
+        for c in range(len(circuits)):
+            assert np.array_equal(states[c].view(np.uint8), ref[c].view(np.uint8)), (share, bar, c)
+        assert np.abs(norms - 1).max() < 1e-5
+    b.free()
