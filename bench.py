@@ -145,7 +145,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--parts", default="all", help="all | fused (profiling runs)")
+    ap.add_argument("--parts", default="all",
+                    help="all | fused | batch (profiling runs: the fused sweeps only, or the batched part only)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain part")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -158,6 +159,9 @@ def main():
     from synth import circuits as S
 
     torch.cuda.set_device(0)
+    if args.parts == "batch":
+        print(json.dumps({"parts": "batch", "batched_learned": batch_learned(Q, S)}), flush=True)
+        return
     stream = torch.cuda.Stream()  # default priority
     n = N_QUBITS
     amp = 16
@@ -255,7 +259,8 @@ def main():
     achieved = 2 * amp * N / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "k_dense<double,4> (fused 4-qubit block sweep)",
+                "kernel": "fused 4-qubit block sweeps (k_dense_lds<double,4> / k_dense<double,4> per the tuned "
+                          "table, k_diag for diagonal blocks), average over the step's launches",
                 "avg_launch_ms": round(sweep_ms, 4), "bytes_per_launch": 2 * amp * N}
 
     # at-scale consistency (untimed): gate-level QFT then emulated inverse
