@@ -402,7 +402,7 @@ int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
  *   QS_TUNE_FFT_DIGIT (dtype, -, -, n bucket): largest FFT digit (bits per
  *     pass), 2..10.
  *   QS_TUNE_FFT_LDS_KB (dtype, -, -, n bucket): LDS tile budget of an FFT
- *     pass, 8..64 KiB.
+ *     pass, 8..160 KiB (default 80: two workgroups per CU).
  *   QS_TUNE_MFMA_WG_PER_CU (complex64, k = 6, -, n bucket): persistent grid
  *     of the matrix-core sweep in workgroups per compute unit, 1..16.
  *   QS_TUNE_BATCH_GANG_SHARE (-, -, -, -): a batch circuit's gang is sized
@@ -410,6 +410,9 @@ int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
  *     workgroup, 1..256.
  *   QS_TUNE_BATCH_BARRIER_AMPS (-, -, -, -): cost of a gang barrier, in
  *     amplitude-op units, used to order the batch queue.
+ *   QS_TUNE_FFT_KERNEL (dtype, -, -, n bucket): FFT pass kernel: 1 one
+ *     workgroup per tile (default), 2 persistent workgroups that prefetch
+ *     the next tile into registers.
  * Index dimensions: dtype QS_C64/QS_C128; k 0..QS_MAX_K; class
  * QS_TCLS_* of the lowest target; n bucket 0 (n < 22), 1 (22..27),
  * 2 (n >= 28). Dimensions a parameter ignores are read at index 0.
@@ -418,7 +421,7 @@ int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
 enum qs_tune_param { QS_TUNE_SWEEP_PATH = 0, QS_TUNE_SWEEP_WG_PER_CU = 1, QS_TUNE_FFT_DIGIT = 2,
                      QS_TUNE_FFT_LDS_KB = 3, QS_TUNE_MFMA_WG_PER_CU = 4,
                      QS_TUNE_BATCH_GANG_SHARE = 5, QS_TUNE_BATCH_BARRIER_AMPS = 6,
-                     QS_TUNE_COUNT = 7 };
+                     QS_TUNE_FFT_KERNEL = 7, QS_TUNE_COUNT = 8 };
 /* Target classes: lowest target inside a 128-byte line, inside a wave's
  * 64 consecutive amplitudes, or above bit 5. */
 enum qs_tune_class { QS_TCLS_SUBLINE = 0, QS_TCLS_SUBWAVE = 1, QS_TCLS_HIGH = 2 };

@@ -135,20 +135,26 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
 def tune_fft(timer, dtype, n, nb, reps, margin, log):
     st = Q.State(n, dtype, stream=timer.stream.cuda_stream)
     times = {}
-    for digit in (6, 7, 8, 9, 10):
-        for kb in (16, 32, 64):
-            Q.tune_set(Q.QS_TUNE_FFT_DIGIT, digit, dtype, 0, 0, nb)
-            Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, kb, dtype, 0, 0, nb)
-            times[(digit, kb)] = timer.ms(lambda: st.emulate_qft(0, n), reps)
+    for kern in (1, 2):
+        for digit in (7, 8, 9, 10):
+            for kb in (40, 80, 160):
+                Q.tune_set(Q.QS_TUNE_FFT_KERNEL, kern, dtype, 0, 0, nb)
+                Q.tune_set(Q.QS_TUNE_FFT_DIGIT, digit, dtype, 0, 0, nb)
+                Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, kb, dtype, 0, 0, nb)
+                times[(kern, digit, kb)] = timer.ms(lambda: st.emulate_qft(0, n), reps)
     st.free()
-    best = _pick(times, (10, 64), margin)
-    Q.tune_set(Q.QS_TUNE_FFT_DIGIT, best[0], dtype, 0, 0, nb)
-    Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, best[1], dtype, 0, 0, nb)
-    log("fft %s n=%d: best digit %d lds %d KiB (%.3f ms; default %.3f ms)" %
-        (DT_NAME[dtype], n, best[0], best[1], times[best], times[(10, 64)]))
-    ms = {"%d/%d" % a: round(b, 4) for a, b in times.items()}
-    return [{"param": "fft_digit", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": best[0], "ms": ms},
-            {"param": "fft_lds_kb", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": best[1]}]
+    dflt = (1, 10, 80)
+    best = _pick(times, dflt, margin)
+    vals = best if best != dflt else (0, 0, 0)
+    Q.tune_set(Q.QS_TUNE_FFT_KERNEL, vals[0], dtype, 0, 0, nb)
+    Q.tune_set(Q.QS_TUNE_FFT_DIGIT, vals[1], dtype, 0, 0, nb)
+    Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, vals[2], dtype, 0, 0, nb)
+    log("fft %s n=%d: best kernel %d digit %d lds %d KiB (%.3f ms; default %.3f ms)" %
+        (DT_NAME[dtype], n, best[0], best[1], best[2], times[best], times[dflt]))
+    ms = {"%d/%d/%d" % a: round(b, 4) for a, b in times.items()}
+    return [{"param": "fft_kernel", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": vals[0], "ms": ms},
+            {"param": "fft_digit", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": vals[1]},
+            {"param": "fft_lds_kb", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": vals[2]}]
 
 
 def tune_mfma(timer, n, nb, reps, margin, log, rng):

@@ -41,7 +41,7 @@ using fftdev::PassArgs;
 constexpr int kBT = 256;      // threads per workgroup
 constexpr int kNS = 13;       // largest LDS-resident circuit (complex64)
 constexpr size_t kLds = size_t(8) << kNS;  // 64 KiB
-constexpr size_t kFftLds = 32 * 1024;      // FFT tile budget inside the batch kernel
+constexpr size_t kFftLds = kLds;           // FFT tile budget inside the batch kernel (its dynamic LDS)
 
 enum OpType { OP_INIT = 0, OP_DENSE = 1, OP_DIAG = 2, OP_FFT_LDS = 3, OP_FFT_PASS = 4, OP_PERM = 5,
               OP_NORM = 6 };

@@ -28,10 +28,11 @@ Range range_of(int p)
     case QS_TUNE_SWEEP_PATH: return {1, 3};
     case QS_TUNE_SWEEP_WG_PER_CU: return {1, 4096};
     case QS_TUNE_FFT_DIGIT: return {2, 10};
-    case QS_TUNE_FFT_LDS_KB: return {8, 64};
+    case QS_TUNE_FFT_LDS_KB: return {8, 160};
     case QS_TUNE_MFMA_WG_PER_CU: return {1, 16};
     case QS_TUNE_BATCH_GANG_SHARE: return {1, 256};
     case QS_TUNE_BATCH_BARRIER_AMPS: return {1, 1 << 24};
+    case QS_TUNE_FFT_KERNEL: return {1, 2};
     default: return {0, -1};
     }
 }

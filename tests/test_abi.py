@@ -140,7 +140,7 @@ def test_tune_table_set_get_and_wildcards(clean_tune):
     (0, -1, -1, -1, 3, 1),                     # n bucket
     (0, -1, -1, -1, -1, 4),                    # path value
     (2, -1, -1, -1, -1, 11),                   # FFT digit
-    (3, -1, -1, -1, -1, 128),                  # FFT LDS KiB
+    (3, -1, -1, -1, -1, 200),                  # FFT LDS KiB
     (4, -1, -1, -1, -1, 17),                   # MFMA WG/CU
 ])
 def test_tune_set_rejects_bad_arguments(clean_tune, args):
