@@ -10,7 +10,7 @@
 // accumulation) carry it.
 //
 // Workgroup: 4 waves, persistent over tiles of 64 groups (4096 amplitudes,
-// 32 KiB). The tile spans index bits 0..5, the block qubits above bit 5 and
+// 32 KiB); the next tile is prefetched into registers during the MFMA loop. The tile spans index bits 0..5, the block qubits above bit 5 and
 // the lowest free bits above 5 (as many as there are block qubits below 6),
 // so loads and stores move 64 consecutive amplitudes per wave instruction;
 // an LDS layout switch regroups the tile into 64 columns of 64 amplitudes.
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_dense_mfma6(float2 *__restri
     __shared__ float2 tile[4096];
     __shared__ float xb[128 * 64];
     float *tf = reinterpret_cast<float *>(tile);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = threadIdx.x & 63;
     const int hi = lane >> 5, lo = lane & 31;
 
     // A slice of the real block matrix: row i = 32 wave + lo, k = 2s + hi
@@ -95,14 +95,20 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_dense_mfma6(float2 *__restri
         colpos[h] = p;
     }
 
+    // load layout: lane = bits 0..5, register r = 16 wave + q; the next
+    // tile's amplitudes are fetched into registers while this one runs on
+    // the matrix cores
+    float2 pre[16];
+    auto fetch = [&](IT tt) {
+        const float2 *gs = psi + expand_tile<IT>(tt, ta) + lane;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) pre[q] = gs[ta.offl[16 * wave + q]];
+    };
+    if (IT(blockIdx.x) < n_tiles) fetch(IT(blockIdx.x));
     for (IT t = IT(blockIdx.x); t < n_tiles; t += IT(gridDim.x)) {
         float2 *g = psi + expand_tile<IT>(t, ta) + lane;
-        // load layout: lane = bits 0..5, register r = 16 wave + q
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = 16 * wave + q;
-            tile[slot(lane + 64 * r)] = g[ta.offl[r]];
-        }
+        for (int q = 0; q < 16; ++q) tile[slot(lane + 64 * (16 * wave + q))] = pre[q];
         __syncthreads();
         // regroup into real form: thread -> (local index j, group col), lanes
         // take consecutive groups so the xb writes are conflict free
@@ -118,6 +124,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_dense_mfma6(float2 *__restri
             xb[(j + 64) * 64 + col] = x.y;
         }
         __syncthreads();
+        if (t + IT(gridDim.x) < n_tiles) fetch(t + IT(gridDim.x));   // each tile has one owner
         v16f acc[2] = {v16f{0}, v16f{0}};
         const float *bp = xb + hi * 64 + lo;
         // two independent accumulation chains (column halves) interleaved;
