@@ -183,10 +183,12 @@ int qs_plan_fusion(const qs_circuit *c, int n_qubits, int max_k, int *n_blocks,
  * any handle of the same qubit count, any number of times. */
 int qs_compile(qs_handle h, const qs_circuit *c, int max_k, qs_program *out);
 
-/* Number of blocks and, if block_k != NULL, their widths; bytes_per_run:
- * algorithmic HBM bytes one run moves for the handle's dtype (read + write of
- * every amplitude each block touches). */
-int qs_program_info(qs_program p, int *n_blocks, int *block_k, double *bytes_per_run);
+/* Number of blocks and, if block_k != NULL, their widths; amp_moves_per_run:
+ * amplitude reads plus writes one run makes (every block reads and writes
+ * all 2^n amplitudes). A program has no dtype of its own, so multiply by the
+ * amplitude size of the handle it runs on (16 B complex128, 8 B complex64)
+ * for the algorithmic HBM bytes. */
+int qs_program_info(qs_program p, int *n_blocks, int *block_k, double *amp_moves_per_run);
 
 /* Copy the composed FP64 matrix of block b (2^(2k+1) doubles) and its
  * ascending qubit list (k ints) to the host. */
@@ -324,7 +326,8 @@ int qs_batch_set_plan(qs_batch b, const int *options);
  * quarter of the average work per workgroup (at most a quarter of the
  * grid, at least 2^12 amplitudes per member). wall_ms: launch time
  * (HIP events); seg_us (per segment, optional): device time of each segment
- * from the in-kernel real-time counter; norms / z0 (per circuit, optional):
+ * from the in-kernel real-time counter (0 for a segment with no ops, such as
+ * an empty gate list); norms / z0 (per circuit, optional):
  * sum |a|^2 and <Z_0>, FP64 accumulated, summed over gang members in a
  * fixed order. Returns QS_EDEVICE if a gang barrier waited more than 5 s
  * (the kernel then gives up and drains; the states are invalid). */

@@ -16,6 +16,8 @@ Contents
 * ``MLP``: FP64 NumPy forward/backward/Adam of the 24-64-64-4 cost model,
   with central finite differences.
 * Cost models of Sec. III-B (Eqs. 1 and 2) and the Table 2 crossover rule.
+* Per-index forms for spot checks at sizes the full simulation cannot
+  reach: ``modmul_source`` and ``layer_amplitudes``.
 """
 from __future__ import annotations
 
@@ -156,6 +158,42 @@ def modmul(psi, work_lo, w, ctrl_lo, c, a, N):
     psi = _c128(psi)
     out = np.zeros_like(psi)
     _chk(lib().or_modmul(_p(psi), _p(out), _nq(psi), work_lo, w, ctrl_lo, c, int(a), int(N)))
+    return out
+
+
+def modmul_source(idx, work_lo, w, ctrl_lo, c, a, N):
+    """Per-index form of the controlled modular multiplication (Sec. III-A):
+    for each output index i, the input index whose amplitude lands there.
+    With x' the work-register value of i and c_val its control value,
+    x' < N came from x = a^(-c_val) x' mod N; x' >= N is fixed. Python
+    integers, one index at a time."""
+    out = []
+    wm = (1 << w) - 1
+    for i in (int(v) for v in idx):
+        xp = (i >> work_lo) & wm
+        cv = (i >> ctrl_lo) & ((1 << c) - 1) if c else 0
+        if xp < N:
+            x = (pow(int(a), -cv, int(N)) * xp) % N
+            i = (i & ~(wm << work_lo)) | (x << work_lo)
+        out.append(i)
+    return np.array(out, dtype=np.uint64)
+
+
+def layer_amplitudes(one_qubit, cz_pairs, idx):
+    """Amplitudes, at the given basis indices, of one random layer applied
+    to |0...0>: single-qubit gates U_q on every qubit (a product state whose
+    qubit-q factor is the first column of U_q, Sec. II) followed by CZ on
+    disjoint pairs (each contributes -1 when both of its bits are 1)."""
+    cols = [np.asarray(u, dtype=np.complex128)[:, 0] for u in one_qubit]
+    out = np.empty(len(idx), dtype=np.complex128)
+    for j, i in enumerate(int(v) for v in idx):
+        amp = 1.0 + 0.0j
+        for q, col in enumerate(cols):
+            amp *= col[(i >> q) & 1]
+        for qa, qb in cz_pairs:
+            if (i >> qa) & 1 and (i >> qb) & 1:
+                amp = -amp
+        out[j] = amp
     return out
 
 

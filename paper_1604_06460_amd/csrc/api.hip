@@ -499,14 +499,14 @@ int qs_compile(qs_handle h, const qs_circuit *c, int max_k, qs_program *out)
     return QS_OK;
 }
 
-int qs_program_info(qs_program p, int *n_blocks, int *block_k, double *bytes_per_run)
+int qs_program_info(qs_program p, int *n_blocks, int *block_k, double *amp_moves_per_run)
 {
     clear_error();
     if (!p) return fail(QS_EINVAL, "NULL program");
     if (n_blocks) *n_blocks = p->n_blocks;
     if (block_k)
         for (int b = 0; b < p->n_blocks; ++b) block_k[b] = p->k[size_t(b)];
-    if (bytes_per_run) *bytes_per_run = double(p->n_blocks) * 2.0 * std::ldexp(1.0, p->n);
+    if (amp_moves_per_run) *amp_moves_per_run = double(p->n_blocks) * 2.0 * std::ldexp(1.0, p->n);
     return QS_OK;
 }
 

@@ -282,9 +282,11 @@ __device__ __forceinline__ uint32_t perm_src(uint32_t i, const BOp &op, const ui
 
 // counter[0]: queue head, counter[1]: error flag, then one barrier counter
 // per circuit
-__global__ void k_reset(unsigned *counter, int n)
+__global__ void k_reset(unsigned *counter, int n, uint64_t *ticks, int n_ticks)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counter[i] = 0;
+    // segments without ops (an empty gate list) report zero time
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_ticks; i += gridDim.x * blockDim.x) ticks[i] = 0;
 }
 
 __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2 *__restrict__ B,
@@ -1086,7 +1088,9 @@ int qs_batch_run(qs_batch b, double *wall_ms, double *seg_us, double *norms, dou
     hipEvent_t e0, e1;
     QS_HIP(hipEventCreate(&e0));
     QS_HIP(hipEventCreate(&e1));
-    hipLaunchKernelGGL(k_reset, dim3(std::min((n_cnt + 255) / 256, 1024)), dim3(256), 0, b->stream, b->d_counter, n_cnt);
+    const int n_ticks = int(b->segs.size());
+    hipLaunchKernelGGL(k_reset, dim3(std::min((std::max(n_cnt, n_ticks) + 255) / 256, 1024)), dim3(256), 0, b->stream,
+                       b->d_counter, n_cnt, b->d_ticks, n_ticks);
     QS_HIP(hipGetLastError());
     QS_HIP(hipEventRecord(e0, b->stream));
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), kLds, b->stream, b->A, b->B, b->d_circ, b->d_tickets,

@@ -249,6 +249,7 @@ class Program:
         return self._h
 
     def info(self):
+        """(block count, block widths, amplitude reads + writes per run)."""
         nb = _I(0)
         by = _D(0)
         _chk(_L.qs_program_info(self._h, C.byref(nb), None, C.byref(by)))

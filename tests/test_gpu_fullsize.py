@@ -1,0 +1,95 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: 30-qubit states, circuits compiled into k = 4 blocks with the tuned
+launch table in effect, the 20-bit-work / 8-bit-control modmul. The oracle
+cannot simulate 2^30 amplitudes gate by gate in a test, so sampled outputs
+are checked against its per-index forms, and whole-state properties (norm,
+an inverse circuit returning |0...0>) that hold at any size."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N = 30
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_1604_06460_amd import qs
+    return qs
+
+
+def _sample(n, count, seed):
+    idx = np.random.default_rng(seed).integers(0, 1 << n, count).astype(np.uint64)
+    idx[:3] = [0, (1 << n) - 1, 1 << (n - 1)]
+    return idx
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_30q_random_layer_fused_k4_sampled_vs_oracle(Q, O, S, dtype):
+    rng = np.random.default_rng(S.SEED_BASE + 11)
+    gates = S.random_layer_on(list(range(N)), rng)
+    ones = [g.matrix for g in gates if g.k == 1]
+    pairs = [tuple(g.targets) for g in gates if g.k == 2]
+    st = Q.State(N, dtype)
+    prog = st.compile(gates, 4)
+    st.run(prog)
+    prog.free()
+    idx = _sample(N, 512, 5)
+    got = st.amplitudes(idx).astype(np.complex128)
+    ref = O.layer_amplitudes(ones, pairs, idx)
+    scale = np.abs(ref).max()
+    tol = 1e-10 if dtype == 1 else 2e-5
+    assert np.abs(got - ref).max() < tol * scale
+    assert abs(st.norm2() - 1) < (1e-12 if dtype == 1 else 1e-5)
+    # marginals of 8 qubits: CZ only changes signs, so they factor
+    qubits = [0, 3, 7, 11, 16, 22, 27, 29]
+    _, p = st.measure(qubits, [0.5])
+    p_ref = np.ones(1)
+    for q in qubits:          # outcome bit r = qubit qubits[r]: later qubits are more significant
+        pq = np.abs(ones[q][:, 0]) ** 2
+        p_ref = np.concatenate([p_ref * pq[0], p_ref * pq[1]])
+    assert np.abs(p - p_ref).max() < (1e-12 if dtype == 1 else 1e-5)
+    st.free()
+
+
+def test_30q_bench_circuit_then_inverse_returns_to_zero(Q, S):
+    """The benchmark's depth-30 circuit, compiled at k = 4, followed by its
+    inverse (reversed gates, conjugate transposes): |0...0> again."""
+    gates = S.random_layer_circuit(N, 30, S.SEED_BASE + 1)
+    inv = [dataclasses.replace(g, matrix=np.ascontiguousarray(g.matrix.conj().T)) for g in reversed(gates)]
+    st = Q.State(N, Q.QS_C128)
+    for gl in (gates, inv):
+        prog = st.compile(gl, 4)
+        nb, ks, moves = prog.info()
+        assert nb > 100 and max(ks) <= 4 and moves == nb * 2.0 * 2 ** N
+        st.run(prog)
+        prog.free()
+    a = st.amplitudes(_sample(N, 64, 9))
+    assert abs(a[0] - 1) < 1e-10
+    assert np.abs(a[1:]).max() < 1e-10
+    assert abs(st.norm2() - 1) < 1e-10
+    st.free()
+
+
+def test_30q_modmul_sampled_bit_exact(Q, O, S):
+    """The benchmark's permutation (work qubits 0..19, control 20..27) on a
+    resident seeded state: every sampled output is exactly the input
+    amplitude at the oracle's source index."""
+    import torch
+    a, Nmod = S.modmul_params(20, S.SEED_BASE + 1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(S.SEED_BASE + 1)
+    x = torch.randn(1 << N, dtype=torch.complex128, device="cuda", generator=gen)
+    st = Q.State(N, Q.QS_C128)
+    st.load_device(x.data_ptr())
+    st.emulate_modmul(0, 20, 20, 8, a, Nmod)
+    idx = _sample(N, 4096, 13)
+    src = O.modmul_source(idx, 0, 20, 20, 8, a, Nmod)
+    want = x[torch.from_numpy(src.astype(np.int64)).to("cuda")].cpu().numpy()
+    got = st.amplitudes(idx)
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+    st.free()
+    del x
+    torch.cuda.empty_cache()

@@ -398,3 +398,29 @@ def test_adam_first_step_is_signed_lr():
     v = [np.zeros(3)]
     MLP.adam(p, g, m, v, 1, lr=0.01)
     assert np.abs(p[0] - (np.array([1.0, -2.0, 3.0]) - 0.01 * np.sign(g[0]))).max() < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Per-index forms used for full-size spot checks
+# ---------------------------------------------------------------------------
+def test_modmul_source_matches_the_permutation(O, S):
+    for (w, c, work_lo, ctrl_lo, n, seed) in [(5, 3, 0, 5, 9, 1), (4, 0, 2, 0, 7, 2), (3, 2, 4, 0, 8, 3)]:
+        a, N = S.modmul_params(w, seed)
+        psi = S.normal_state(n, seed)
+        out = O.modmul(psi, work_lo, w, ctrl_lo, c, a, N)
+        src = O.modmul_source(np.arange(1 << n), work_lo, w, ctrl_lo, c, a, N)
+        assert np.array_equal(out, psi[src.astype(np.int64)])
+        assert np.array_equal(np.sort(src), np.arange(1 << n, dtype=np.uint64))   # a bijection
+
+
+def test_layer_amplitudes_match_gate_by_gate_simulation(O, S):
+    rng = np.random.default_rng(12)
+    n = 9
+    gates = S.random_layer_on(list(range(n)), rng)
+    ones = [g.matrix for g in gates if g.k == 1]
+    pairs = [tuple(g.targets) for g in gates if g.k == 2]
+    assert len(ones) == n and len(pairs) == n // 2
+    assert [g.targets[0] for g in gates if g.k == 1] == list(range(n))
+    psi = O.apply_circuit(S.zero_state(n), gates)
+    idx = np.arange(1 << n)
+    assert np.abs(O.layer_amplitudes(ones, pairs, idx) - psi).max() < 1e-13
