@@ -395,9 +395,11 @@ int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
  *   QS_TUNE_SWEEP_PATH (dtype, k, class, n bucket): kernel for an
  *     uncontrolled dense k-qubit block: 1 thread per group (registers),
  *     2 wave tiles staged through LDS (needs n >= 6 + k; k <= 5 for
- *     complex128), 3 FP32 matrix cores (complex64, k = 6, n >= 12). A path
- *     that does not apply to a block falls back to the default rule (LDS
- *     below the line size, matrix cores for complex64 k = 6, registers
+ *     complex128), 3 FP32 matrix cores (complex64, k = 6, n >= 12),
+ *     4 workgroup tiles with the output rows split over the waves (k >= 5,
+ *     n >= 6 + k). A path that does not apply to a block falls back to the
+ *     default rule (matrix cores for complex64 k = 6, workgroup tiles for
+ *     other blocks of 5 or 6 qubits, LDS below the line size, registers
  *     otherwise). Every path computes the same products; only the
  *     summation order of the FP32/FP64 dot products may differ.
  *   QS_TUNE_SWEEP_WG_PER_CU (dtype, k, class, n bucket): cap of the dense

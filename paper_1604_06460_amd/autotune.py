@@ -5,7 +5,8 @@
 Times candidate launch parameters on the current device and writes the JSON
 table that the binding applies at import (qs.TUNED_FILE):
 
-  * dense sweep path (registers / LDS-staged wave tiles / matrix cores) and
+  * dense sweep path (registers / LDS-staged wave tiles / matrix cores /
+    workgroup tiles with rows split over waves) and
     the grid cap in workgroups per CU, per (dtype, k, class of the lowest
     target, n bucket);
   * FFT digit width and LDS tile budget per (dtype, n bucket);
@@ -96,9 +97,9 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
         mat = random_unitary(k, rng)
         for cls in (Q.QS_TCLS_SUBLINE, Q.QS_TCLS_SUBWAVE, Q.QS_TCLS_HIGH):
             sets = class_targets(cls, k, n, dtype)
-            paths = [1, 2] + ([3] if dtype == Q.QS_C64 and k == 6 else [])
+            paths = [1, 2] + ([3] if dtype == Q.QS_C64 and k == 6 else []) + ([4] if k >= 5 else [])
             if dtype == Q.QS_C128 and k == 6:
-                paths = [1]
+                paths = [1, 4]
 
             def run_sets():
                 for t in sets:
@@ -116,7 +117,7 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
                             "value": int(path), "ms": {str(a): round(b, 4) for a, b in times.items()}})
             # grid cap for the chosen path (the matrix-core path has its own)
             gtimes = {}
-            if path != 3 and not (path == 0 and dtype == Q.QS_C64 and k == 6):
+            if path in (1, 2, 4) or (path == 0 and k <= 4):
                 for g in (0, 8, 32, 128):
                     Q.tune_set(Q.QS_TUNE_SWEEP_WG_PER_CU, g, dtype, k, cls, nb)
                     gtimes[g] = timer.ms(run_sets, reps)

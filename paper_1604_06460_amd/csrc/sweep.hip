@@ -175,6 +175,89 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict_
     }
 }
 
+// Dense sweep for wide blocks (K = 5, 6) whose groups do not fit one
+// thread's registers. A workgroup of 4 waves shares the tile of k_dense_lds
+// (2^(6+K) amplitudes, loaded and stored 64 consecutive amplitudes per
+// instruction) in LDS; lane l owns group l of the tile and wave w computes
+// output rows [w D/4, (w+1) D/4) of all 64 groups. The group's inputs are
+// read from LDS 8 at a time and each output row's 8-entry matrix chunk
+// arrives through scalar loads (SGPR operands), issued one row ahead; a
+// scheduling barrier after each row keeps the compiler from hoisting every
+// chunk into SGPRs.
+template <typename R, int K, typename IT>
+__global__ __launch_bounds__(256) void k_dense_wide(typename V2<R>::T *__restrict__ psi,
+                                                    const R *__restrict__ mat, IT n_tiles,
+                                                    FixArgs fx, OffArgs<(1 << K)> offl,
+                                                    LdsArgs<(1 << K)> la)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K, RW = D / 4;
+    __shared__ C2 tile[64 * D];
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = int(threadIdx.x) & 63;
+    int lp = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) lp |= ((lane >> b) & 1) << la.lane_pos[b];
+    for (IT t = IT(blockIdx.x); t < n_tiles; t += IT(gridDim.x)) {
+        C2 *p = psi + expand<IT>(t, fx) + lane;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int rr = wave * RW + q;
+            tile[lds_slot<C2>(lane + 64 * rr)] = p[offl.o[rr]];
+        }
+        __syncthreads();
+        R re[RW], im[RW];
+#pragma unroll
+        for (int jj = 0; jj < RW; ++jj) re[jj] = im[jj] = R(0);
+#pragma unroll 1
+        for (int c = 0; c < D / 8; ++c) {
+            C2 x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = tile[lds_slot<C2>(lp | la.offc[8 * c + i])];
+            // row chunks one ahead: the next row's scalar loads are in
+            // flight while the current row's FMAs run
+            const R *rows = mat + 2 * (wave * RW * D + 8 * c);
+            R cur[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cur[i] = rows[i];
+#pragma unroll
+            for (int jj = 0; jj < RW; ++jj) {
+                R nxt[16];
+                if (jj + 1 < RW) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) nxt[i] = rows[2 * D * (jj + 1) + i];
+                }
+                // four independent FMA chains per row
+                R ra = re[jj], rb = R(0), ia = im[jj], ib = R(0);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const R mr = cur[2 * i], mi = cur[2 * i + 1];
+                    ra = fma(mr, x[i].x, ra);
+                    rb = fma(-mi, x[i].y, rb);
+                    ia = fma(mr, x[i].y, ia);
+                    ib = fma(mi, x[i].x, ib);
+                }
+                re[jj] = ra + rb;
+                im[jj] = ia + ib;
+                if (jj + 1 < RW) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) cur[i] = nxt[i];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        __syncthreads();   // every wave has read the inputs of the tile
+#pragma unroll
+        for (int jj = 0; jj < RW; ++jj) tile[lds_slot<C2>(lp | la.offc[wave * RW + jj])] = C2{re[jj], im[jj]};
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int rr = wave * RW + q;
+            p[offl.o[rr]] = tile[lds_slot<C2>(lane + 64 * rr)];
+        }
+        __syncthreads();
+    }
+}
+
 // Dense sweep for groups too wide to keep in one thread's registers: the
 // 2^K outputs of a group are split over D/OUTS lanes of the same wave. Every
 // lane reads the whole group (cache hits after the first lane) and the
@@ -384,11 +467,16 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
         if ((path == 0 || path == 3) && mfma_applicable(h, d)) return launch_dense_mfma(h, d, dmat);
     }
     // by default, targets inside a 128-byte line stage the tile through LDS
+    // (one wave per tile); wide complex128 blocks share a tile per workgroup
     constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
     constexpr bool lds_capable = (sizeof(R) == 8) ? (K <= 5) : (K <= 6);
-    if constexpr (lds_capable) {
-        const bool lds_ok = d.ctrl_mask == 0 && h->n >= 6 + K;
-        if (lds_ok && (path == 2 || (path != 1 && mint < kLineBits))) {
+    constexpr bool wide_capable = K >= 5;
+    constexpr bool wide_default = K >= 5;
+    const bool tile_ok = d.ctrl_mask == 0 && h->n >= 6 + K;
+    const bool use_wide = wide_capable && tile_ok && (path == 4 || (path == 0 && wide_default));
+    const bool use_lds = lds_capable && tile_ok && !use_wide && (path == 2 || (path != 1 && path != 4 && mint < kLineBits));
+    if (use_wide || use_lds) {
+        {
             uint64_t tmask = 0;
             for (int i = 0; i < K; ++i) tmask |= 1ull << d.targets[i];
             int klo = 0;
@@ -425,8 +513,14 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
             if (int rc = make_fix(P.data(), int(P.size()), 0, ft)) return rc;
             const IT n_tiles = IT(h->dim() >> (6 + K));
             const unsigned grid = capped(std::min<uint64_t>(uint64_t(n_tiles), 1ull << 22));
-            hipLaunchKernelGGL((k_dense_lds<R, K, IT>), dim3(grid), dim3(64), 0, h->stream, psi,
-                               m, n_tiles, ft, offl, la);
+            if (use_wide) {
+                if constexpr (wide_capable)
+                    hipLaunchKernelGGL((k_dense_wide<R, K, IT>), dim3(grid), dim3(256), 0, h->stream, psi, m,
+                                       n_tiles, ft, offl, la);
+            } else if constexpr (lds_capable) {
+                hipLaunchKernelGGL((k_dense_lds<R, K, IT>), dim3(grid), dim3(64), 0, h->stream, psi,
+                                   m, n_tiles, ft, offl, la);
+            }
             QS_HIP(hipGetLastError());
             return QS_OK;
         }

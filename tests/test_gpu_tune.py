@@ -47,7 +47,7 @@ def test_every_sweep_path_matches_oracle(Q, O, S, dtype, k):
         assert Q.tune_classify(dtype, n, t)[0] == cls
         m = _unitary(k, rng)
         ref = O.apply_gate(psi0.copy(), t, m)
-        for path in (1, 2, 3):
+        for path in (1, 2, 3, 4):
             for cap in (0, 1):          # cap 1: one workgroup per CU, grid-stride
                 Q.tune_set(Q.QS_TUNE_SWEEP_PATH, path, dtype, k, cls, -1)
                 Q.tune_set(Q.QS_TUNE_SWEEP_WG_PER_CU, cap, dtype, k, cls, -1)
