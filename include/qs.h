@@ -418,6 +418,10 @@ int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
  *   QS_TUNE_FFT_KERNEL (dtype, -, -, n bucket): FFT pass kernel: 1 one
  *     workgroup per tile (default), 2 persistent workgroups that prefetch
  *     the next tile into registers.
+ *   QS_TUNE_SWEEP_NT (dtype, k, class, n bucket): cache policy of the
+ *     register and LDS-staged dense sweeps: bit 0 nontemporal (streaming)
+ *     stores, bit 1 nontemporal loads; 0 plain accesses.
+ *   QS_TUNE_FFT_NT (dtype, -, -, n bucket): the same for the FFT passes.
  * Index dimensions: dtype QS_C64/QS_C128; k 0..QS_MAX_K; class
  * QS_TCLS_* of the lowest target; n bucket 0 (n < 22), 1 (22..27),
  * 2 (n >= 28). Dimensions a parameter ignores are read at index 0.
@@ -426,7 +430,8 @@ int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
 enum qs_tune_param { QS_TUNE_SWEEP_PATH = 0, QS_TUNE_SWEEP_WG_PER_CU = 1, QS_TUNE_FFT_DIGIT = 2,
                      QS_TUNE_FFT_LDS_KB = 3, QS_TUNE_MFMA_WG_PER_CU = 4,
                      QS_TUNE_BATCH_GANG_SHARE = 5, QS_TUNE_BATCH_BARRIER_AMPS = 6,
-                     QS_TUNE_FFT_KERNEL = 7, QS_TUNE_COUNT = 8 };
+                     QS_TUNE_FFT_KERNEL = 7, QS_TUNE_SWEEP_NT = 8, QS_TUNE_FFT_NT = 9,
+                     QS_TUNE_COUNT = 10 };
 /* Target classes: lowest target inside a 128-byte line, inside a wave's
  * 64 consecutive amplitudes, or above bit 5. */
 enum qs_tune_class { QS_TCLS_SUBLINE = 0, QS_TCLS_SUBWAVE = 1, QS_TCLS_HIGH = 2 };

@@ -6,7 +6,7 @@ Times candidate launch parameters on the current device and writes the JSON
 table that the binding applies at import (qs.TUNED_FILE):
 
   * dense sweep path (registers / LDS-staged wave tiles / matrix cores /
-    workgroup tiles with rows split over waves) and
+    workgroup tiles with rows split over waves), its cache policy and
     the grid cap in workgroups per CU, per (dtype, k, class of the lowest
     target, n bucket);
   * FFT digit width and LDS tile budget per (dtype, n bucket);
@@ -34,6 +34,10 @@ import numpy as np
 from . import qs as Q
 
 BUCKET_N = {Q.QS_C128: (20, 26, 30), Q.QS_C64: (20, 26, 30)}
+# The cache policy changes only how lines are allocated, so its timings
+# repeat closely (well under 1 % between runs) and a smaller margin than
+# for launch shapes is enough to keep noise from flipping it.
+NT_MARGIN = 0.01
 DT_NAME = {Q.QS_C64: "c64", Q.QS_C128: "c128"}
 
 
@@ -126,9 +130,19 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
                 entries.append({"param": "sweep_wg_per_cu", "dtype": dtype, "k": k, "cls": cls,
                                 "nbucket": nb, "value": int(g),
                                 "ms": {str(a): round(b, 4) for a, b in gtimes.items()}})
-            log("sweep %s n=%d k=%d cls=%d: path %s %s grid %s" %
+            # cache policy of the register and LDS-staged paths
+            ntimes = {}
+            if path in (1, 2) or (path == 0 and k <= 4):
+                for ntv in (0, 1, 2, 3):
+                    Q.tune_set(Q.QS_TUNE_SWEEP_NT, ntv, dtype, k, cls, nb)
+                    ntimes[ntv] = timer.ms(run_sets, reps)
+                ntv = _pick(ntimes, 0, NT_MARGIN)
+                Q.tune_set(Q.QS_TUNE_SWEEP_NT, ntv, dtype, k, cls, nb)
+                entries.append({"param": "sweep_nt", "dtype": dtype, "k": k, "cls": cls, "nbucket": nb,
+                                "value": int(ntv), "ms": {str(a): round(b, 4) for a, b in ntimes.items()}})
+            log("sweep %s n=%d k=%d cls=%d: path %s %s grid %s nt %s" %
                 (DT_NAME[dtype], n, k, cls, path, {a: round(b, 3) for a, b in times.items()},
-                 {a: round(b, 3) for a, b in gtimes.items()}))
+                 {a: round(b, 3) for a, b in gtimes.items()}, {a: round(b, 3) for a, b in ntimes.items()}))
     st.free()
     return entries
 
@@ -150,12 +164,23 @@ def tune_fft(timer, dtype, n, nb, reps, margin, log):
     Q.tune_set(Q.QS_TUNE_FFT_KERNEL, vals[0], dtype, 0, 0, nb)
     Q.tune_set(Q.QS_TUNE_FFT_DIGIT, vals[1], dtype, 0, 0, nb)
     Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, vals[2], dtype, 0, 0, nb)
-    log("fft %s n=%d: best kernel %d digit %d lds %d KiB (%.3f ms; default %.3f ms)" %
-        (DT_NAME[dtype], n, best[0], best[1], best[2], times[best], times[dflt]))
+    st = Q.State(n, dtype, stream=timer.stream.cuda_stream)
+    ntimes = {}
+    for ntv in (0, 1, 2, 3):
+        Q.tune_set(Q.QS_TUNE_FFT_NT, ntv, dtype, 0, 0, nb)
+        ntimes[ntv] = timer.ms(lambda: st.emulate_qft(0, n), reps)
+    st.free()
+    ntv = _pick(ntimes, 0, NT_MARGIN)
+    Q.tune_set(Q.QS_TUNE_FFT_NT, ntv, dtype, 0, 0, nb)
+    log("fft %s n=%d: best kernel %d digit %d lds %d KiB (%.3f ms; default %.3f ms); nt %d %s" %
+        (DT_NAME[dtype], n, best[0], best[1], best[2], times[best], times[dflt], ntv,
+         {a: round(b, 3) for a, b in ntimes.items()}))
     ms = {"%d/%d/%d" % a: round(b, 4) for a, b in times.items()}
     return [{"param": "fft_kernel", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": vals[0], "ms": ms},
             {"param": "fft_digit", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": vals[1]},
-            {"param": "fft_lds_kb", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": vals[2]}]
+            {"param": "fft_lds_kb", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": vals[2]},
+            {"param": "fft_nt", "dtype": dtype, "k": 0, "cls": 0, "nbucket": nb, "value": int(ntv),
+             "ms": {str(a): round(b, 4) for a, b in ntimes.items()}}]
 
 
 def tune_mfma(timer, n, nb, reps, margin, log, rng):

@@ -149,6 +149,8 @@ int run_fft(qs_state *h, int q_lo, int m, int inverse)
     if (int rc = plan_passes(h->n, q_lo, m, inverse, shape.digit, shape.lds, sizeof(C2), passes,
                              stream ? StreamRho<R>::value : FftRho<R>::value))
         return rc;
+    const int nt = tune_value(QS_TUNE_FFT_NT, h->dtype, 0, 0, tune_nbucket(h->n));
+    for (auto &pa : passes) pa.nt = nt;
     const int P = int(passes.size());
     if (P > 1)
         if (int rc = ensure_scratch(h)) return rc;

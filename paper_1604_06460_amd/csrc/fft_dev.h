@@ -22,6 +22,33 @@ template <typename R> struct V2;
 template <> struct V2<double> { using T = double2; };
 template <> struct V2<float> { using T = float2; };
 
+template <typename C2> struct NtVec;
+template <> struct NtVec<double2> { typedef double __attribute__((ext_vector_type(2))) T; };
+template <> struct NtVec<float2> { typedef float __attribute__((ext_vector_type(2))) T; };
+
+template <typename C2>
+__device__ __forceinline__ C2 load_amp(const C2 *p, int nt)
+{
+    if (nt & 2) {
+        using T = typename NtVec<C2>::T;
+        const T v = __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
+        return C2{v.x, v.y};
+    }
+    return *p;
+}
+
+template <typename C2>
+__device__ __forceinline__ void store_amp(C2 *p, C2 v, int nt)
+{
+    if (nt & 1) {
+        using T = typename NtVec<C2>::T;
+        const T w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<T *>(p));
+    } else {
+        *p = v;
+    }
+}
+
 template <typename C2>
 __device__ __forceinline__ C2 cmul(C2 a, C2 b)
 {
@@ -48,6 +75,7 @@ struct PassArgs {
     int ndig;
     int dpos[8], dw[8], doff[8];
     uint64_t tiles;     // number of tiles of this pass
+    int nt;             // cache policy: bit 0 nontemporal stores, bit 1 nontemporal loads
 };
 
 // Column pad (elements) of the LDS tile: a column stride congruent to
@@ -289,7 +317,7 @@ __device__ void tile_load(const typename V2<R>::T *__restrict__ src, const PassA
     const int L = 1 << pa.r;
     for (int i = 0; i < th.reps; ++i) {
         const int l = th.l0 + i * th.lstep;
-        if (l < L) T.tile[phys(th.c0, l, T.S)] = s0[uint64_t(l) << pa.dig_lo];
+        if (l < L) T.tile[phys(th.c0, l, T.S)] = load_amp(s0 + (uint64_t(l) << pa.dig_lo), pa.nt);
     }
 }
 
@@ -309,7 +337,7 @@ __device__ void tile_store(typename V2<R>::T *__restrict__ dst, const PassArgs &
         C2 v = T.tile[phys(c0, T.row[l], T.S)];
         if (pa.tw_bits) v = cmul(v, (l >> 5) ? cmul(ga[l & 31], gb[l >> 5]) : ga[l]);
         if (pa.scale != 1.0) v = C2{R(double(v.x) * pa.scale), R(double(v.y) * pa.scale)};
-        d0[T.dbits[l]] = v;
+        store_amp(d0 + T.dbits[l], v, pa.nt);
     }
 }
 

@@ -39,6 +39,35 @@ template <typename R> struct V2;
 template <> struct V2<double> { using T = double2; };
 template <> struct V2<float> { using T = float2; };
 
+// Nontemporal (streaming) loads and stores of one amplitude, selected by a
+// tuning flag: bit 0 stores, bit 1 loads.
+template <typename C2> struct NtVec;
+template <> struct NtVec<double2> { typedef double __attribute__((ext_vector_type(2))) T; };
+template <> struct NtVec<float2> { typedef float __attribute__((ext_vector_type(2))) T; };
+
+template <typename C2>
+__device__ __forceinline__ C2 load_amp(const C2 *p, int nt)
+{
+    if (nt & 2) {
+        using T = typename NtVec<C2>::T;
+        const T v = __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
+        return C2{v.x, v.y};
+    }
+    return *p;
+}
+
+template <typename C2>
+__device__ __forceinline__ void store_amp(C2 *p, C2 v, int nt)
+{
+    if (nt & 1) {
+        using T = typename NtVec<C2>::T;
+        const T w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<T *>(p));
+    } else {
+        *p = v;
+    }
+}
+
 template <typename IT>
 __device__ __forceinline__ IT expand(IT g, const FixArgs &f)
 {
@@ -96,7 +125,7 @@ __device__ __forceinline__ void row_dot(const R *__restrict__ row, const C2 (&v)
 template <typename R, int K, typename IT>
 __global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict__ psi,
                                                   const R *__restrict__ mat, IT n_groups,
-                                                  FixArgs fx, OffArgs<(1 << K)> off)
+                                                  FixArgs fx, OffArgs<(1 << K)> off, int nt)
 {
     using C2 = typename V2<R>::T;
     constexpr int D = 1 << K;
@@ -105,12 +134,12 @@ __global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict_
         C2 *p = psi + expand<IT>(g, fx);
         C2 v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = p[off.o[j]];
+        for (int j = 0; j < D; ++j) v[j] = load_amp(p + off.o[j], nt);
 #pragma unroll 1
         for (int j = 0; j < D; ++j) {
             R re = R(0), im = R(0);
             row_dot<R, C2, D>(mat + 2 * j * D, v, re, im);
-            p[off.o[j]] = C2{re, im};
+            store_amp(p + off.o[j], C2{re, im}, nt);
         }
     }
 }
@@ -143,7 +172,7 @@ template <typename R, int K, typename IT>
 __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict__ psi,
                                                   const R *__restrict__ mat, IT n_tiles,
                                                   FixArgs fx, OffArgs<(1 << K)> offl,
-                                                  LdsArgs<(1 << K)> la)
+                                                  LdsArgs<(1 << K)> la, int nt)
 {
     using C2 = typename V2<R>::T;
     constexpr int D = 1 << K;
@@ -156,7 +185,7 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict_
         C2 *p = psi + expand<IT>(t, fx) + lane;
         C2 v[D];
 #pragma unroll
-        for (int r = 0; r < D; ++r) v[r] = p[offl.o[r]];
+        for (int r = 0; r < D; ++r) v[r] = load_amp(p + offl.o[r], nt);
 #pragma unroll
         for (int r = 0; r < D; ++r) tile[lds_slot<C2>(lane + 64 * r)] = v[r];
         __syncthreads();
@@ -170,7 +199,7 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict_
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < D; ++r) p[offl.o[r]] = tile[lds_slot<C2>(lane + 64 * r)];
+        for (int r = 0; r < D; ++r) store_amp(p + offl.o[r], tile[lds_slot<C2>(lane + 64 * r)], nt);
         __syncthreads();
     }
 }
@@ -458,6 +487,7 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
     const int cls = tune_class(mint, h->dtype), nb = tune_nbucket(h->n);
     const int path = tune_value(QS_TUNE_SWEEP_PATH, h->dtype, K, cls, nb);
     const int wg_per_cu = tune_value(QS_TUNE_SWEEP_WG_PER_CU, h->dtype, K, cls, nb);
+    const int nt = tune_value(QS_TUNE_SWEEP_NT, h->dtype, K, cls, nb);
     auto capped = [&](uint64_t g) {
         if (wg_per_cu) g = std::min<uint64_t>(g, uint64_t(wg_per_cu) * uint64_t(device_cus()));
         return unsigned(std::max<uint64_t>(g, 1));
@@ -519,7 +549,7 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
                                        n_tiles, ft, offl, la);
             } else if constexpr (lds_capable) {
                 hipLaunchKernelGGL((k_dense_lds<R, K, IT>), dim3(grid), dim3(64), 0, h->stream, psi,
-                                   m, n_tiles, ft, offl, la);
+                                   m, n_tiles, ft, offl, la, nt);
             }
             QS_HIP(hipGetLastError());
             return QS_OK;
@@ -531,7 +561,7 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
                            dim3(kBlock), 0, h->stream, psi, m, n_groups, fx, off);
     } else {
         hipLaunchKernelGGL((k_dense<R, K, IT>), dim3(capped(grid_for(n_groups))), dim3(kBlock), 0,
-                           h->stream, psi, m, n_groups, fx, off);
+                           h->stream, psi, m, n_groups, fx, off, nt);
     }
     QS_HIP(hipGetLastError());
     return QS_OK;

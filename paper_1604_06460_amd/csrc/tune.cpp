@@ -33,6 +33,8 @@ Range range_of(int p)
     case QS_TUNE_BATCH_GANG_SHARE: return {1, 256};
     case QS_TUNE_BATCH_BARRIER_AMPS: return {1, 1 << 24};
     case QS_TUNE_FFT_KERNEL: return {1, 2};
+    case QS_TUNE_SWEEP_NT: return {1, 3};
+    case QS_TUNE_FFT_NT: return {1, 3};
     default: return {0, -1};
     }
 }

@@ -48,15 +48,16 @@ def test_every_sweep_path_matches_oracle(Q, O, S, dtype, k):
         m = _unitary(k, rng)
         ref = O.apply_gate(psi0.copy(), t, m)
         for path in (1, 2, 3, 4):
-            for cap in (0, 1):          # cap 1: one workgroup per CU, grid-stride
+            for cap, nt in ((0, 0), (1, 3)):   # cap 1: one workgroup per CU, grid-stride; nt 3: streaming
                 Q.tune_set(Q.QS_TUNE_SWEEP_PATH, path, dtype, k, cls, -1)
                 Q.tune_set(Q.QS_TUNE_SWEEP_WG_PER_CU, cap, dtype, k, cls, -1)
+                Q.tune_set(Q.QS_TUNE_SWEEP_NT, nt, dtype, k, cls, -1)
                 st = Q.State(n, dtype)
                 st.set(psi0)
                 st.apply_gate(t, m)
                 got = st.get().astype(np.complex128)
                 st.free()
-                assert np.abs(got - ref).max() < TOL[dtype], (dtype, k, cls, path, cap)
+                assert np.abs(got - ref).max() < TOL[dtype], (dtype, k, cls, path, cap, nt)
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
@@ -66,9 +67,10 @@ def test_every_fft_shape_matches_oracle(Q, O, S, dtype):
     for q_lo, m in ((0, 15), (2, 11)):
         ref = O.dft_numpy(psi0, q_lo, m, False)
         for digit in (2, 4, 7, 10):
-            for kb in (8, 64):
+            for kb, nt in ((8, 0), (64, 3), (160, 1)):
                 Q.tune_set(Q.QS_TUNE_FFT_DIGIT, digit, dtype)
                 Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, kb, dtype)
+                Q.tune_set(Q.QS_TUNE_FFT_NT, nt, dtype)
                 st = Q.State(n, dtype)
                 st.set(psi0)
                 st.emulate_qft(q_lo, m)
