@@ -93,3 +93,19 @@ def test_30q_modmul_sampled_bit_exact(Q, O, S):
     st.free()
     del x
     torch.cuda.empty_cache()
+
+
+def test_28q_modmul_configuration_full_state_bit_exact(Q, O, S):
+    """The 28-qubit arithmetic workload: control register (qubits 20..27) in
+    uniform superposition, seeded normal 20-qubit work register, an odd
+    20-bit modulus. All 2^28 outputs against the oracle, bit for bit."""
+    a, Nmod = S.modmul_params(20, S.SEED_BASE + 2)
+    w = S.normal_state(20, S.SEED_BASE + 2)
+    psi = np.tile(w, 256) / 16.0                      # H on each control qubit: amplitude 1/16
+    st = Q.State(28, Q.QS_C128)
+    st.set(psi)
+    st.emulate_modmul(0, 20, 20, 8, a, Nmod)
+    got = st.get()
+    st.free()
+    ref = O.modmul(psi, 0, 20, 20, 8, a, Nmod)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
