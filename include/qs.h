@@ -388,6 +388,41 @@ enum qs_policy { QS_POLICY_HEURISTIC = 0, QS_POLICY_LEARNED = 1, QS_POLICY_FIXED
 int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
 
 /* ---------------------------------------------------------------------- */
+/* Dense unitaries and the controlled powers of phase estimation          */
+/* ---------------------------------------------------------------------- */
+
+/* Sec. III-C: b-bit phase estimation needs U^1, U^2, ..., U^(2^(b-1)); a
+ * simulator runs the G gates of U 2^b - 1 times, an emulator builds the
+ * dense matrix of U once and squares it. */
+typedef struct qs_unitary_t *qs_unitary;
+
+/* Build the dense 2^m x 2^m complex128 matrix of the gate list c, which must
+ * act on qubits [0, m) only (1 <= m <= 15): the identity is swept as a
+ * 2m-qubit work state by the fused program of c (max_k as qs_compile), so
+ * column j becomes U e_j. Device memory: 16 * 4^m bytes (twice that once
+ * squared). Synchronous on hip_stream. */
+int qs_unitary_build(const qs_circuit *c, int m, int max_k, void *hip_stream, qs_unitary *out);
+int qs_unitary_info(qs_unitary u, int *m);
+/* U <- U U (FP64 complex GEMM from the BLAS library), on the build stream. */
+int qs_unitary_square(qs_unitary u);
+/* Copy U to the host: 2^m x 2^m complex128, row-major, (re, im) interleaved
+ * like gate matrices (U[r][c] maps basis state c to r). */
+int qs_unitary_get(qs_unitary u, double *host_dst);
+/* Apply U to qubits [0, m) of the state where qubit ctrl (m <= ctrl < n) is
+ * 1: one strided-batched GEMM over the state viewed as a 2^m x 2^(n-m)
+ * column-major matrix, FP64 for complex128 states, FP32 (U rounded once)
+ * for complex64. Writes the second buffer and swaps (a borrowed buffer is
+ * refreshed by a device copy). */
+int qs_apply_controlled_unitary(qs_handle h, qs_unitary u, int ctrl);
+int qs_unitary_free(qs_unitary u);
+/* The controlled powers of QPE by repeated squaring: for j = 0 .. b-1,
+ * U^(2^j) controlled by qubit ctrl_lo + j (the register [ctrl_lo,
+ * ctrl_lo + b) must lie above qubit m - 1). The Hadamards on the control
+ * register and the inverse QFT (qs_emulate_qft with inverse = 1) are the
+ * caller's. */
+int qs_emulate_qpe_powers(qs_handle h, const qs_circuit *c, int m, int ctrl_lo, int b, int max_k);
+
+/* ---------------------------------------------------------------------- */
 /* Launch-parameter table (filled by an autotuner, read by the dispatchers) */
 /* ---------------------------------------------------------------------- */
 

@@ -18,6 +18,8 @@ Contents
 * Cost models of Sec. III-B (Eqs. 1 and 2) and the Table 2 crossover rule.
 * Per-index forms for spot checks at sizes the full simulation cannot
   reach: ``modmul_source`` and ``layer_amplitudes``.
+* ``qpe_powers``: the controlled powers of phase estimation applied gate by
+  gate, 2^j runs of U per control qubit (Sec. III-C).
 """
 from __future__ import annotations
 
@@ -286,6 +288,21 @@ def block_matrix(k, gates_local):
     for g in gates_local:
         U = full_matrix(k, g.targets, g.matrix, g.ctrl_mask, g.ctrl_vals) @ U
     return U
+
+
+def qpe_powers(psi, gates, ctrl_lo, b):
+    """The controlled powers of phase estimation as a simulator applies them
+    (Sec. III-C): for j = 0 .. b-1 the gate list of U runs 2^j times, every
+    gate controlled by qubit ctrl_lo + j."""
+    from types import SimpleNamespace
+    psi = _c128(psi).copy()
+    for j in range(b):
+        c = 1 << (ctrl_lo + j)
+        cg = [SimpleNamespace(targets=tuple(g.targets), matrix=g.matrix, ctrl_mask=int(g.ctrl_mask) | c,
+                              ctrl_vals=int(g.ctrl_vals) | c) for g in gates]
+        for _ in range(1 << j):
+            psi = apply_circuit(psi, cg)
+    return psi
 
 
 def dft_numpy(psi, q_lo=0, m=None, inverse=False):

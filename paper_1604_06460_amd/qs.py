@@ -557,3 +557,67 @@ def load_tuning(path=TUNED_FILE):
 
 if os.path.exists(TUNED_FILE):
     load_tuning(TUNED_FILE)
+
+
+# ---------------------------------------------------------------------------
+# Dense unitaries and the controlled powers of phase estimation
+# ---------------------------------------------------------------------------
+_sig("qs_unitary_build", [C.POINTER(Circuit), _I, _I, _P, C.POINTER(_P)])
+_sig("qs_unitary_info", [_P, C.POINTER(_I)])
+_sig("qs_unitary_square", [_P])
+_sig("qs_unitary_get", [_P, _P])
+_sig("qs_apply_controlled_unitary", [_P, _P, _I])
+_sig("qs_unitary_free", [_P])
+_sig("qs_emulate_qpe_powers", [_P, C.POINTER(Circuit), _I, _I, _I, _I])
+
+
+class Unitary:
+    """Dense 2^m x 2^m matrix of a gate list on qubits [0, m), on the device."""
+
+    def __init__(self, gates, m, max_k=4, stream=None):
+        pc = PackedCircuit(gates)
+        h = _P()
+        _chk(_L.qs_unitary_build(C.byref(pc.c), int(m), int(max_k), stream, C.byref(h)))
+        self._h = h
+        self.m = int(m)
+
+    def square(self):
+        _chk(_L.qs_unitary_square(self._h))
+
+    def get(self):
+        d = 1 << self.m
+        out = np.empty((d, d), dtype=np.complex128)
+        _chk(_L.qs_unitary_get(self._h, _ptr(out)))
+        return out
+
+    def apply_controlled(self, state, ctrl):
+        _chk(_L.qs_apply_controlled_unitary(state.handle, self._h, int(ctrl)))
+
+    def free(self):
+        if self._h:
+            _L.qs_unitary_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def emulate_qpe_powers(state, gates, m, ctrl_lo, b, max_k=4):
+    """U^(2^j) controlled by qubit ctrl_lo + j for j < b, by repeated squaring."""
+    pc = PackedCircuit(gates)
+    _chk(_L.qs_emulate_qpe_powers(state.handle, C.byref(pc.c), int(m), int(ctrl_lo), int(b), int(max_k)))
+
+
+def qpe_crossover_bits(t_apply, t_build, t_op, per_bit=True, bmax=200):
+    """Precision (bits) from which emulated phase estimation is no slower than
+    simulation (Sec. III-C, the rule behind Table 2): the simulator applies U
+    2^b - 1 times; the emulator builds U once and then pays t_op per bit
+    (a squaring) or once (an eigendecomposition)."""
+    for b in range(1, bmax + 1):
+        emu = t_build + (b * t_op if per_bit else t_op)
+        if (2 ** b - 1) * t_apply >= emu:
+            return b
+    return None

@@ -155,6 +155,27 @@ def qft_circuit(m: int, q_lo: int = 0, inverse: bool = False, swaps: bool = True
     return inverse_circuit(gates) if inverse else gates
 
 
+def mat_rx(theta: float) -> np.ndarray:
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
+
+
+def tfim_trotter_step(m: int, J: float = 1.0, hx: float = 0.7, dt: float = 0.1):
+    """One first-order Trotter step of the 1D transverse-field Ising model on
+    qubits 0..m-1 (open chain): Rx(2 hx dt) on every qubit, then for each
+    neighbouring pair (q, q+1) the ZZ rotation exp(-i J dt Z Z) written as
+    CNOT(q -> q+1), Rz(2 J dt) on q+1, CNOT(q -> q+1). That is m + 3(m-1) =
+    4m - 3 gates, the gate count of the phase-estimation example of Table 2
+    (the paper gives only the model and the count; this decomposition is
+    ours)."""
+    gates = [Gate((q,), mat_rx(2 * hx * dt), name="Rx") for q in range(m)]
+    for q in range(m - 1):
+        gates.append(Gate((q + 1, q), MAT_CNOT.copy(), name="CNOT"))
+        gates.append(Gate((q + 1,), mat_rz(2 * J * dt), name="Rz"))
+        gates.append(Gate((q + 1, q), MAT_CNOT.copy(), name="CNOT"))
+    return gates
+
+
 def ghz_circuit(n: int):
     """The entangling operation of Sec. IV-E: H on the first qubit, then a
     CNOT from it onto every other qubit."""

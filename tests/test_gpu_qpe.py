@@ -1,0 +1,89 @@
+"""Dense unitaries and the controlled powers of phase estimation on the GPU
+(Sec. III-C) against the oracle: the dense matrix of a gate list, its
+square, a controlled application at every kind of control position, and
+the emulated powers against the gate-level ones (2^j runs of U)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 2e-5, 1: 1e-11}
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_1604_06460_amd import qs
+    return qs
+
+
+def _circuit(S, m, seed):
+    rng = np.random.default_rng(seed)
+    g = [S.Gate((q,), S.haar_2x2(rng)) for q in range(m)]
+    g += [S.cnot(q, (q + 1) % m) for q in range(m)] if m > 1 else []
+    g += [S.Gate((q,), S.haar_2x2(rng)) for q in range(m)]
+    return g
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 7])
+@pytest.mark.parametrize("max_k", [1, 4])
+def test_dense_unitary_and_square_vs_oracle(Q, O, S, m, max_k):
+    gates = _circuit(S, m, 10 + m)
+    ref = O.block_matrix(m, gates)
+    u = Q.Unitary(gates, m, max_k)
+    assert np.abs(u.get() - ref).max() < 1e-12
+    u.square()
+    assert np.abs(u.get() - ref @ ref).max() < 1e-11
+    u.free()
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_controlled_unitary_every_control_position(Q, O, S, dtype):
+    m, n = 3, 11
+    gates = _circuit(S, m, 3)
+    U = O.block_matrix(m, gates)
+    u = Q.Unitary(gates, m)
+    psi0 = S.normal_state(n, 6)
+    for ctrl in (m, m + 1, 6, n - 1):
+        st = Q.State(n, dtype)
+        st.set(psi0)
+        u.apply_controlled(st, ctrl)
+        ref = O.full_matrix(n, list(range(m)), U, 1 << ctrl, 1 << ctrl) @ psi0
+        assert np.abs(st.get() - ref).max() < TOL[dtype], ctrl
+        st.free()
+    with pytest.raises(Q.QSError):
+        u.apply_controlled(Q.State(n, dtype), m - 1)      # control inside the register
+    u.free()
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+@pytest.mark.parametrize("m,b,n", [(4, 4, 9), (2, 5, 8), (6, 3, 10)])
+def test_emulated_powers_equal_gate_level(Q, O, S, dtype, m, b, n):
+    gates = S.tfim_trotter_step(m, dt=0.3)
+    psi0 = S.normal_state(n, 7 + m)
+    ref = O.qpe_powers(psi0, gates, m, b)
+    st = Q.State(n, dtype)
+    st.set(psi0)
+    Q.emulate_qpe_powers(st, gates, m, m, b)
+    assert np.abs(st.get() - ref).max() < 10 * TOL[dtype]
+    st.free()
+
+
+def test_phase_estimation_end_to_end(Q, S):
+    """Eigen qubit |1> of diag(1, e^{2 pi i k / 2^b}): Hadamards, emulated
+    powers, emulated inverse QFT -> the control register reads k exactly."""
+    b, k = 6, 45
+    gates = [S.Gate((0,), np.diag([1.0, np.exp(2j * np.pi * k / 2 ** b)]))]
+    st = Q.State(1 + b, Q.QS_C128)
+    st.apply_gates([S.g1(S.MAT_X, 0)] + [S.g1(S.MAT_H, 1 + j) for j in range(b)])
+    Q.emulate_qpe_powers(st, gates, 1, 1, b)
+    st.emulate_qft(1, b, inverse=True)
+    psi = st.get()
+    assert abs(abs(psi[(k << 1) | 1]) - 1) < 1e-12
+    st.free()
+
+
+def test_unitary_rejects_gates_outside_the_register(Q, S):
+    with pytest.raises(Q.QSError):
+        Q.Unitary([S.g1(S.MAT_H, 3)], 3)
+    with pytest.raises(Q.QSError):
+        Q.Unitary([S.mcx([4], 0)], 3)

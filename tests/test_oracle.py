@@ -424,3 +424,52 @@ def test_layer_amplitudes_match_gate_by_gate_simulation(O, S):
     psi = O.apply_circuit(S.zero_state(n), gates)
     idx = np.arange(1 << n)
     assert np.abs(O.layer_amplitudes(ones, pairs, idx) - psi).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Phase estimation: the gate-level controlled powers (Sec. III-C)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("b,k", [(3, 5), (4, 11), (5, 1)])
+def test_qpe_powers_phase_kickback_closed_form(O, S, b, k):
+    """U = diag(1, exp(2 pi i k / 2^b)) on an eigen qubit |1>: H on the b
+    control qubits, the controlled powers, then the inverse QFT leave the
+    control register exactly in |k>."""
+    phase = np.diag([1.0, np.exp(2j * np.pi * k / 2 ** b)])
+    gates = [S.Gate((0,), phase)]
+    n = 1 + b
+    psi = S.zero_state(n)
+    psi = O.apply_circuit(psi, [S.g1(S.MAT_X, 0)] + [S.g1(S.MAT_H, 1 + j) for j in range(b)])
+    psi = O.qpe_powers(psi, gates, 1, b)
+    psi = O.qft_direct(psi, 1, b, inverse=True)
+    want = np.zeros(1 << n, dtype=np.complex128)
+    want[(k << 1) | 1] = 1.0
+    assert np.abs(psi - want).max() < 1e-12
+
+
+def test_qpe_powers_equal_dense_matrix_powers(O, S):
+    rng = np.random.default_rng(21)
+    m, b = 3, 3
+    gates = [S.Gate((q,), S.haar_2x2(rng)) for q in range(m)] + [S.cnot(0, 2), S.cz(1, 2)]
+    U = O.block_matrix(m, gates)
+    n = m + b
+    psi0 = S.normal_state(n, 4)
+    ref = psi0.copy()
+    for j in range(b):
+        V = np.linalg.matrix_power(U, 2 ** j)
+        ref = O.full_matrix(n, list(range(m)), V, 1 << (m + j), 1 << (m + j)) @ ref
+    assert np.abs(O.qpe_powers(psi0, gates, m, b) - ref).max() < 1e-12
+
+
+def test_tfim_step_has_4m_minus_3_gates_and_is_unitary(O, S):
+    for m in (2, 5, 8):
+        g = S.tfim_trotter_step(m)
+        assert len(g) == 4 * m - 3
+    U = O.block_matrix(5, S.tfim_trotter_step(5))
+    assert np.abs(U.conj().T @ U - np.eye(32)).max() < 1e-12
+
+
+def test_library_crossover_rule_matches_the_oracle_on_table2(O):
+    from paper_1604_06460_amd import qs as Q
+    for n, G, ta, tb, tg, te, xs, xe in _table2():
+        assert Q.qpe_crossover_bits(ta, tb, tg, True) == O.qpe_crossover(ta, tb, tg, True) == int(xs)
+        assert Q.qpe_crossover_bits(ta, tb, te, False) == O.qpe_crossover(ta, tb, te, False) == int(xe)
