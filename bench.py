@@ -139,6 +139,86 @@ def batch_learned(Q, S):
             "max_abs_err_vs_oracle": err, "circuits_checked": checked}
 
 
+def qpe_table(Q, S, ms=(8, 9, 10, 11, 12, 13, 14)):
+    """Phase estimation of a 1D transverse-field Ising Trotter step (4m-3
+    gates) on m qubits, the example of Table 2, timed on this GPU:
+    applying controlled U once to an (m+1)-qubit state,
+    building the dense U, one FP64 squaring; the crossover precision follows
+    from the rule behind Table 2. Then one whole b-bit estimate both ways at
+    m = 10, b = 10 (state of 20 qubits): the controlled powers simulated
+    (2^b - 1 runs of U) against the emulated ones, each followed by the
+    emulated inverse QFT. Simulation runs U as a program fused into blocks of
+    up to 4 qubits, the simulator's fastest form."""
+    import torch
+    out = {"unit": "ms", "rows": []}
+    stream = torch.cuda.Stream()
+
+    def timed(fn, reps=3):
+        fn()
+        stream.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    for m in ms:
+        gates = S.tfim_trotter_step(m)
+        ctl = [S.Gate(g.targets, g.matrix, g.ctrl_mask | (1 << m), g.ctrl_vals | (1 << m)) for g in gates]
+        st = Q.State(m + 1, Q.QS_C128, stream=stream.cuda_stream)
+        prog = st.compile(ctl, 4)
+        t_apply = timed(lambda: st.run(prog))
+        prog.free()
+        st.free()
+        t_build = timed(lambda: Q.Unitary(gates, m, 4, stream=stream.cuda_stream).free(), reps=2)
+        u = Q.Unitary(gates, m, 4, stream=stream.cuda_stream)
+        t_sq = timed(u.square, reps=2)
+        u.free()
+        torch.cuda.empty_cache()
+        out["rows"].append({"m": m, "gates": len(gates), "t_apply_ms": round(t_apply, 4),
+                            "t_build_ms": round(t_build, 4), "t_square_ms": round(t_sq, 4),
+                            "crossover_bits_squaring": Q.qpe_crossover_bits(t_apply, t_build, t_sq, True)})
+        log("qpe m=%d: apply %.3f ms, build %.3f ms, square %.3f ms" % (m, t_apply, t_build, t_sq))
+    m, b = 10, 10
+    gates = S.tfim_trotter_step(m)
+    n = m + b
+    psi = S.normal_state(m, 5)
+
+    def run(emulate):
+        st = Q.State(n, Q.QS_C128, stream=stream.cuda_stream)
+        st.set(np.kron(np.ones(1 << b) / 2 ** (b / 2), psi))   # Hadamards on the control register
+        t0 = time.perf_counter()
+        if emulate:
+            Q.emulate_qpe_powers(st, gates, m, m, b)
+        else:
+            for j in range(b):
+                c = 1 << (m + j)
+                prog = st.compile([S.Gate(g.targets, g.matrix, c, c) for g in gates], 4)
+                for _ in range(1 << j):
+                    st.run(prog)
+                prog.free()
+        st.emulate_qft(m, b, inverse=True)
+        st.sync()
+        dt = (time.perf_counter() - t0) * 1e3
+        probs = st.measure(list(range(m, n)))[1]
+        st.free()
+        return dt, probs
+
+    run(False)                       # warm-up: library handles, code objects
+    run(True)
+    t_gate, p_gate = run(False)
+    t_emu, p_emu = run(True)
+    out["estimate"] = {"m": m, "b": b, "simulated_ms": round(t_gate, 2), "emulated_ms": round(t_emu, 2),
+                       "speedup": round(t_gate / t_emu, 1),
+                       "max_abs_diff_phase_distribution": float(np.abs(p_gate - p_emu).max())}
+    log("qpe estimate m=%d b=%d: simulated %.1f ms, emulated %.1f ms" % (m, b, t_gate, t_emu))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,8 +226,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parts", default="all",
-                    help="all | fused | batch (profiling runs: the fused sweeps only, or the batched part only)")
+                    help="all | fused | batch | qpe (profiling runs: one part only)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain part")
+    ap.add_argument("--no-qpe", action="store_true", help="skip the phase-estimation part")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state-vector path is not sharded "
@@ -161,6 +242,9 @@ def main():
     torch.cuda.set_device(0)
     if args.parts == "batch":
         print(json.dumps({"parts": "batch", "batched_learned": batch_learned(Q, S)}), flush=True)
+        return
+    if args.parts == "qpe":
+        print(json.dumps({"parts": "qpe", "phase_estimation": qpe_table(Q, S)}), flush=True)
         return
     stream = torch.cuda.Stream()  # default priority
     n = N_QUBITS
@@ -292,6 +376,9 @@ def main():
     batched = None
     if not args.no_batch and parts_all:
         batched = batch_learned(Q, S)
+    qpe = None
+    if not args.no_qpe and parts_all:
+        qpe = qpe_table(Q, S)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) starts")
@@ -324,6 +411,7 @@ def main():
         "copy_ceiling_gbs": round(copy_gbs, 1),
         "check": check,
         "batched_learned": batched,
+        "phase_estimation": qpe,
     }
     print(json.dumps(out), flush=True)
 
