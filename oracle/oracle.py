@@ -181,6 +181,73 @@ def modmul_source(idx, work_lo, w, ctrl_lo, c, a, N):
     return np.array(out, dtype=np.uint64)
 
 
+ARITH_MUL, ARITH_DIV = 0, 1
+
+
+def _field(idx, lo, m):
+    return (idx >> np.uint64(lo)) & np.uint64((1 << m) - 1)
+
+
+def arith_dest(idx, kind, a_lo, b_lo, c_lo, m):
+    """Where each basis index goes under the emulated integer multiplication
+    or division of Sec. III-A, for three m-bit registers a, b, c.
+
+    Multiplication: (a, b, c) -> (a, b, c + a*b mod 2^m). With c = 0 this is
+    the map (a, b, 0) -> (a, b, ab), the product cut to the m bits of c.
+
+    Division: with c = 0 the map (a, b, 0) -> (a mod b, b, a div b) of the
+    paper, computed here by integer division; b = 0 (undefined there) gives
+    (a, 0, 2^m - 1), as the reversible restoring division below does. The
+    paper fixes no action for c != 0; we take that of the restoring-division
+    network that a simulator runs (repeated subtraction and shift): with
+    Y = a + 2^m c, for i = m-1 down to 0 the (m+1)-bit window W of Y at bit i
+    becomes W - b mod 2^(m+1); if its top bit is then set, b is added back
+    to its low m bits mod 2^m; the top bit is flipped. The top bits left
+    behind are the quotient bits."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    M0 = np.uint64((1 << m) - 1)
+    a, b, c = _field(idx, a_lo, m), _field(idx, b_lo, m), _field(idx, c_lo, m)
+    if kind == ARITH_MUL:
+        a2, c2 = a, (c + a * b) & M0
+    elif kind == ARITH_DIV:
+        a2, c2 = a.copy(), c.copy()
+        clean = c == 0
+        nz = clean & (b != 0)
+        a2[nz] = a[nz] % b[nz]
+        c2[nz] = a[nz] // b[nz]
+        c2[clean & (b == 0)] = M0
+        # c != 0: step through the network's arithmetic
+        d = ~clean
+        Y = a[d] | (c[d] << np.uint64(m))
+        bd = b[d]
+        M1 = np.uint64((1 << (m + 1)) - 1)
+        top = np.uint64(1 << m)
+        for i in range(m - 1, -1, -1):
+            sh = np.uint64(i)
+            W = (Y >> sh) & M1
+            W = (W - bd) & M1
+            s = W >> np.uint64(m)
+            W = (W & top) | (((W & M0) + s * bd) & M0)
+            W = W ^ top
+            Y = (Y & ~(M1 << sh)) | (W << sh)
+        a2[d] = Y & M0
+        c2[d] = Y >> np.uint64(m)
+    else:
+        raise ValueError("unknown arithmetic kind")
+    keep = ~((M0 << np.uint64(a_lo)) | (M0 << np.uint64(c_lo)))
+    return (idx & keep) | (a2 << np.uint64(a_lo)) | (c2 << np.uint64(c_lo))
+
+
+def arith(psi, kind, a_lo, b_lo, c_lo, m):
+    """The whole state after the emulated multiplication or division: the
+    amplitude at index i moves to arith_dest(i)."""
+    psi = np.asarray(psi)
+    dest = arith_dest(np.arange(psi.size, dtype=np.uint64), kind, a_lo, b_lo, c_lo, m)
+    out = np.zeros_like(psi)
+    out[dest.astype(np.int64)] = psi
+    return out
+
+
 def layer_amplitudes(one_qubit, cz_pairs, idx):
     """Amplitudes, at the given basis indices, of one random layer applied
     to |0...0>: single-qubit gates U_q on every qubit (a product state whose

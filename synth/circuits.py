@@ -387,6 +387,76 @@ def _modmul_gates_on(x, acc, kreg, carry, flag, ctrl, a, N):
     return gates
 
 
+def cuccaro_add_carry_out(areg, breg, carry, top):
+    """b <- a + b over len+1 bits: the ripple-carry adder of cuccaro_add
+    with its final carry XORed into ``top`` (the sum's bit len)."""
+    nb = len(areg)
+    assert len(breg) == nb
+    gates = []
+    cin = carry
+    for i in range(nb):
+        gates += _maj(cin, breg[i], areg[i])
+        cin = areg[i]
+    gates.append(cnot(areg[nb - 1], top))
+    for i in range(nb - 1, -1, -1):
+        prev = carry if i == 0 else areg[i - 1]
+        gates += _uma(prev, breg[i], areg[i])
+    return gates
+
+
+def controlled(gates, ctrl):
+    """Every gate of the list with one more control qubit."""
+    bit = 1 << int(ctrl)
+    return [Gate(g.targets, g.matrix, g.ctrl_mask | bit, g.ctrl_vals | bit, name="c" + g.name)
+            for g in gates]
+
+
+def mul_gate_circuit_on(aq, bq, cq, anc):
+    """Gate-level c <- c + a*b mod 2^m (Sec. III-A: repeated addition and
+    shift): for each bit i of b, the low m-i bits of a are added into bits
+    i..m-1 of c by a Cuccaro adder controlled on b_i. One clean ancilla."""
+    m = len(aq)
+    gates = []
+    for i in range(m):
+        gates += controlled(cuccaro_add(list(aq[:m - i]), list(cq[i:]), anc), bq[i])
+    return gates
+
+
+def div_gate_circuit_on(aq, bq, cq, anc):
+    """Gate-level restoring division (Sec. III-A: repeated subtraction and
+    shift), (a, b, 0) -> (a mod b, b, a div b). Y = a + 2^m c is one 2m-qubit
+    register; for i = m-1 down to 0 the (m+1)-qubit window of Y at bit i
+    has b subtracted (the Cuccaro adder run backwards, carry into the
+    window's top qubit), gets b added back to its low m qubits when its top
+    qubit shows a borrow, and its top qubit is flipped into the quotient
+    bit. One clean ancilla."""
+    m = len(aq)
+    Y = list(aq) + list(cq)
+    gates = []
+    for i in range(m - 1, -1, -1):
+        low, top = Y[i:i + m], Y[i + m]
+        gates += inverse_circuit(cuccaro_add_carry_out(list(bq), low, anc, top))
+        gates += controlled(cuccaro_add(list(bq), low, anc), top)
+        gates.append(g1(MAT_X, top, "X"))
+    return gates
+
+
+def arith_layout(m):
+    """Registers of the multiplication/division workload: a on qubits
+    0..m-1, b on m..2m-1, c on 2m..3m-1; the gate-level networks add one
+    ancilla, qubit 3m."""
+    return list(range(m)), list(range(m, 2 * m)), list(range(2 * m, 3 * m)), 3 * m
+
+
+def arith_input_state(m, seed, extra=0):
+    """a and b in a seeded normal superposition, c = 0, on 3m + extra
+    qubits (extra ancillas clean)."""
+    ab = normal_state(2 * m, seed)
+    psi = np.zeros(1 << (3 * m + extra), dtype=np.complex128)
+    psi[:1 << (2 * m)] = ab
+    return psi
+
+
 def random_layer_on(qubits, rng):
     """One random layer restricted to `qubits`: a Haar 2x2 on each (in the
     listed order), then CZ on disjoint pairs of a random permutation."""

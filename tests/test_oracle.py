@@ -473,3 +473,63 @@ def test_library_crossover_rule_matches_the_oracle_on_table2(O):
     for n, G, ta, tb, tg, te, xs, xe in _table2():
         assert Q.qpe_crossover_bits(ta, tb, tg, True) == O.qpe_crossover(ta, tb, tg, True) == int(xs)
         assert Q.qpe_crossover_bits(ta, tb, te, False) == O.qpe_crossover(ta, tb, te, False) == int(xe)
+
+
+# ---------------------------------------------------------------------------
+# Integer multiplication and division into a third register (Sec. III-A)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
+def test_arith_on_a_clean_c_register_is_product_and_divmod(O, m):
+    """Every (a, b, 0): multiplication leaves a*b mod 2^m in c; division
+    leaves a mod b in a and a div b in c (Python integer arithmetic), and
+    a divisor of 0 gives (a, 0, 2^m - 1)."""
+    M = 1 << m
+    a, b = np.meshgrid(np.arange(M), np.arange(M), indexing="ij")
+    a, b = a.ravel().astype(np.uint64), b.ravel().astype(np.uint64)
+    idx = a | (b << np.uint64(m))
+    got = O.arith_dest(idx, O.ARITH_MUL, 0, m, 2 * m, m)
+    want = [int(x) | (int(y) << m) | (((int(x) * int(y)) % M) << (2 * m)) for x, y in zip(a, b)]
+    assert got.tolist() == want
+    got = O.arith_dest(idx, O.ARITH_DIV, 0, m, 2 * m, m)
+    want = []
+    for x, y in zip(a.tolist(), b.tolist()):
+        q, r = divmod(x, y) if y else (M - 1, x)
+        want.append(r | (y << m) | (q << (2 * m)))
+    assert got.tolist() == want
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("m,lo", [(3, (0, 3, 6)), (4, (8, 0, 4)), (3, (6, 0, 3))])
+def test_arith_is_a_bijection_that_keeps_b(O, kind, m, lo):
+    n = 3 * m
+    idx = np.arange(1 << n, dtype=np.uint64)
+    d = O.arith_dest(idx, kind, *lo, m)
+    assert np.unique(d).size == idx.size
+    bm = np.uint64(((1 << m) - 1) << lo[1])
+    assert np.array_equal(d & bm, idx & bm)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_arith_equals_the_cuccaro_networks_on_every_input(O, S, m, kind):
+    """The repeated-addition and repeated-subtraction Toffoli networks of
+    Sec. III-A (synth: Cuccaro adders, one ancilla) run by the oracle's gate
+    simulator on a random state over all 3m register qubits, c != 0 included,
+    equal the permutation exactly."""
+    aq, bq, cq, anc = S.arith_layout(m)
+    psi = np.zeros(1 << (3 * m + 1), dtype=np.complex128)
+    psi[:1 << (3 * m)] = S.normal_state(3 * m, 30 + m)
+    net = (S.mul_gate_circuit_on if kind == 0 else S.div_gate_circuit_on)(aq, bq, cq, anc)
+    assert all(len(g.targets) <= 2 for g in net)
+    ref = O.apply_circuit(psi, net)
+    assert np.array_equal(O.arith(psi, kind, 0, m, 2 * m, m), ref)
+
+
+def test_arith_gate_counts(S):
+    """Multiplication: sum over bits of b of a (m-i)-bit adder, 6 gates per
+    bit: 3m(m+1). Division: per quotient bit a subtraction with carry-out
+    (6m+1), a controlled addition (6m) and one X: m(12m+2)."""
+    for m in (2, 5, 7):
+        aq, bq, cq, anc = S.arith_layout(m)
+        assert len(S.mul_gate_circuit_on(aq, bq, cq, anc)) == 3 * m * (m + 1)
+        assert len(S.div_gate_circuit_on(aq, bq, cq, anc)) == m * (12 * m + 2)
