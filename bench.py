@@ -219,6 +219,77 @@ def qpe_table(Q, S, ms=(8, 9, 10, 11, 12, 13, 14)):
     return out
 
 
+def arith_table(Q, S, ms=(4, 6, 8, 10)):
+    """Integer multiplication and division of two m-bit registers into a
+    third (Sec. III-A), n = 3m qubits, complex128, registers a, b, c from
+    the most significant qubits down as the paper writes the index: the
+    emulated permutation
+    against the gate-level network a simulator runs on 3m + 1 qubits
+    (Cuccaro adders, one ancilla), applied gate by gate and as a program
+    fused into blocks of up to 4 qubits. a and b start in a seeded normal
+    superposition, c = 0. Times from HIP events on the state's stream."""
+    import torch
+    stream = torch.cuda.Stream()
+
+    def timed(fn, reps):
+        fn()
+        stream.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def input_state(n, m, seed):
+        # a, b in a seeded normal superposition, c = 0, in the arith_layout
+        # order: index = anc.a.b.c from the top
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        x = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
+        v = torch.randn(1 << (2 * m), dtype=torch.complex128, device="cuda", generator=gen)
+        M = 1 << m
+        x.view(-1, M, M, M)[0, :, :, 0] = (v / torch.linalg.vector_norm(v)).view(M, M)
+        st = Q.State(n, Q.QS_C128, stream=stream.cuda_stream)
+        st.load_device(x.data_ptr())
+        st.sync()
+        del x, v
+        return st
+
+    rows = []
+    for m in ms:
+        row = {"m": m, "n_emulated": 3 * m, "n_simulated": 3 * m + 1}
+        aq, bq, cq, anc = S.arith_layout(m)
+        for kind, name, net_fn in ((0, "mul", S.mul_gate_circuit_on), (1, "div", S.div_gate_circuit_on)):
+            net = net_fn(aq, bq, cq, anc)
+            st = input_state(3 * m, m, S.SEED_BASE + 20 + m)
+            op = st.emulate_mul if kind == 0 else st.emulate_div
+            t_emu = timed(lambda: op(aq[0], bq[0], cq[0], m), 3)
+            st.free()
+            torch.cuda.empty_cache()
+            st = input_state(3 * m + 1, m, S.SEED_BASE + 20 + m)
+            reps = 1 if m >= 10 else 2
+            t_gates = timed(lambda: st.apply_gates(net), reps)
+            prog = st.compile(net, 4)
+            blocks = prog.info()[0]
+            t_fused = timed(lambda: st.run(prog), reps)
+            prog.free()
+            st.free()
+            torch.cuda.empty_cache()
+            t_sim = min(t_gates, t_fused)
+            row[name] = {"gates": len(net), "fused_blocks": blocks, "emulated_ms": round(t_emu, 4),
+                         "simulated_gate_by_gate_ms": round(t_gates, 3), "simulated_fused_ms": round(t_fused, 3),
+                         "speedup": round(t_sim / t_emu, 1),
+                         "emulated_gbs": round(2 * 16 * 2 ** (3 * m) / (t_emu * 1e-3) / 1e9, 1)}
+            log("arith m=%d %s: emulated %.3f ms, gate by gate %.1f ms (%d gates), fused %.1f ms (%d blocks)"
+                % (m, name, t_emu, t_gates, len(net), t_fused, blocks))
+        rows.append(row)
+    return {"unit": "ms", "dtype": "c128", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,9 +297,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parts", default="all",
-                    help="all | fused | batch | qpe (profiling runs: one part only)")
+                    help="all | fused | batch | qpe | arith (profiling runs: one part only)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain part")
     ap.add_argument("--no-qpe", action="store_true", help="skip the phase-estimation part")
+    ap.add_argument("--no-arith", action="store_true", help="skip the multiplication/division part")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state-vector path is not sharded "
@@ -245,6 +317,9 @@ def main():
         return
     if args.parts == "qpe":
         print(json.dumps({"parts": "qpe", "phase_estimation": qpe_table(Q, S)}), flush=True)
+        return
+    if args.parts == "arith":
+        print(json.dumps({"parts": "arith", "arithmetic": arith_table(Q, S)}), flush=True)
         return
     stream = torch.cuda.Stream()  # default priority
     n = N_QUBITS
@@ -379,6 +454,9 @@ def main():
     qpe = None
     if not args.no_qpe and parts_all:
         qpe = qpe_table(Q, S)
+    arith = None
+    if not args.no_arith and parts_all:
+        arith = arith_table(Q, S)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) starts")
@@ -412,6 +490,7 @@ def main():
         "check": check,
         "batched_learned": batched,
         "phase_estimation": qpe,
+        "arithmetic": arith,
     }
     print(json.dumps(out), flush=True)
 

@@ -242,6 +242,27 @@ typedef struct qs_perm {
  * or gcd(a, N) != 1. */
 int qs_emulate_permutation(qs_handle h, const qs_perm *p);
 
+/* Integer multiplication and division into a third register (Sec. III-A):
+ * a, b and c are the m-bit fields of the basis index at a_lo, b_lo and c_lo
+ * (least significant bit first).
+ *
+ * QS_ARITH_MUL: (a, b, c) -> (a, b, c + a*b mod 2^m). With c = 0 this is the
+ *   paper's (a, b, 0) -> (a, b, ab), the product cut to the m bits of c.
+ * QS_ARITH_DIV: with c = 0, (a, b, 0) -> (a mod b, b, a div b); a divisor
+ *   b = 0 gives (a, 0, 2^m - 1). For c != 0 the map is that of the
+ *   restoring-division network (repeated subtraction and shift): with
+ *   Y = a + 2^m c, for i = m-1 down to 0 the (m+1)-bit window W of Y at bit
+ *   i becomes W - b mod 2^(m+1); if its top bit is then set, b is added back
+ *   to its low m bits mod 2^m; the top bit is flipped. The result is a + 2^m c
+ *   of the output.
+ *
+ * Both are permutations of basis states: amplitudes move bit-exactly, out of
+ * place through the scratch state as in qs_emulate_permutation. Requires
+ * m >= 1 and three disjoint fields inside the state; otherwise QS_EINVAL and
+ * the state is unchanged. */
+enum qs_arith_kind { QS_ARITH_MUL = 0, QS_ARITH_DIV = 1 };
+int qs_emulate_arith(qs_handle h, int kind, int a_lo, int b_lo, int c_lo, int m);
+
 /* ---------------------------------------------------------------------- */
 /* Measurement quantities (Sec. III-D, Sec. II)                            */
 /* ---------------------------------------------------------------------- */

@@ -145,6 +145,7 @@ int device_cus();
 int ensure_partials(qs_state *h, size_t count);
 int ensure_host_out(qs_state *h, size_t bytes);
 int ensure_scratch(qs_state *h);
+int emulate_arith(qs_state *h, int kind, int a_lo, int b_lo, int c_lo, int m);
 
 }  // namespace qs
 

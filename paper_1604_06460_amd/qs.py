@@ -30,6 +30,7 @@ QS_C64, QS_C128 = 0, 1
 QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED, QS_ENOTUNITARY = range(6)
 QS_MAX_K = 6
 QS_PERM_MODMUL, QS_PERM_TABLE = 0, 1
+QS_ARITH_MUL, QS_ARITH_DIV = 0, 1
 
 _P = C.c_void_p
 _I = C.c_int
@@ -90,6 +91,7 @@ _sig("qs_program_free", [_P])
 _sig("qs_apply_circuit", [_P, C.POINTER(Circuit), _I])
 _sig("qs_emulate_qft", [_P, _I, _I, _I])
 _sig("qs_emulate_permutation", [_P, C.POINTER(Perm)])
+_sig("qs_emulate_arith", [_P, _I, _I, _I, _I, _I])
 _sig("qs_norm2", [_P, C.POINTER(_D)])
 _sig("qs_expectation", [_P, _U64, _U64, _U64, C.POINTER(_D), C.POINTER(_D)])
 _sig("qs_measure", [_P, _I, _P, _I, _P, _P, _P, _I])
@@ -382,6 +384,14 @@ class State:
         d = np.ascontiguousarray(dest, dtype=np.uint64)
         p = Perm(QS_PERM_TABLE, 0, 0, 0, 0, 0, 0, int(lo), int(nbits), _ptr(d))
         _chk(_L.qs_emulate_permutation(self._h, C.byref(p)))
+
+    def emulate_mul(self, a_lo, b_lo, c_lo, m):
+        """(a, b, c) -> (a, b, c + a*b mod 2^m) on three m-bit registers."""
+        _chk(_L.qs_emulate_arith(self._h, QS_ARITH_MUL, int(a_lo), int(b_lo), int(c_lo), int(m)))
+
+    def emulate_div(self, a_lo, b_lo, c_lo, m):
+        """(a, b, 0) -> (a mod b, b, a div b) on three m-bit registers."""
+        _chk(_L.qs_emulate_arith(self._h, QS_ARITH_DIV, int(a_lo), int(b_lo), int(c_lo), int(m)))
 
     def norm2(self):
         out = _D()

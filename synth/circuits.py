@@ -442,19 +442,20 @@ def div_gate_circuit_on(aq, bq, cq, anc):
 
 
 def arith_layout(m):
-    """Registers of the multiplication/division workload: a on qubits
-    0..m-1, b on m..2m-1, c on 2m..3m-1; the gate-level networks add one
-    ancilla, qubit 3m."""
-    return list(range(m)), list(range(m, 2 * m)), list(range(2 * m, 3 * m)), 3 * m
+    """Registers of the multiplication/division workload as the index is
+    written in Sec. III-A, a first and most significant: c on qubits 0..m-1,
+    b on m..2m-1, a on 2m..3m-1. The gate-level networks add one ancilla,
+    qubit 3m. Returns (a qubits, b qubits, c qubits, ancilla)."""
+    return list(range(2 * m, 3 * m)), list(range(m, 2 * m)), list(range(m)), 3 * m
 
 
 def arith_input_state(m, seed, extra=0):
-    """a and b in a seeded normal superposition, c = 0, on 3m + extra
-    qubits (extra ancillas clean)."""
-    ab = normal_state(2 * m, seed)
-    psi = np.zeros(1 << (3 * m + extra), dtype=np.complex128)
-    psi[:1 << (2 * m)] = ab
-    return psi
+    """a and b in a seeded normal superposition, c = 0, in the layout of
+    arith_layout, on 3m + extra qubits (extra ancillas clean)."""
+    ab = normal_state(2 * m, seed).reshape(1 << m, 1 << m)       # [a][b]
+    psi = np.zeros((1 << extra, 1 << m, 1 << m, 1 << m), dtype=np.complex128)   # [anc][a][b][c]
+    psi[0, :, :, 0] = ab
+    return psi.reshape(-1)
 
 
 def random_layer_on(qubits, rng):

@@ -46,6 +46,7 @@ def test_host_side_validation_without_gpu(Q):
     assert L.qs_apply_gate(None, 1, None, None, 0, 0) == Q.QS_EINVAL
     assert "handle" in Q.last_error()
     assert L.qs_emulate_qft(None, 0, 1, 0) == Q.QS_EINVAL
+    assert L.qs_emulate_arith(None, 0, 0, 1, 2, 1) == Q.QS_EINVAL
     assert L.qs_norm2(None, None) == Q.QS_EINVAL
     h = C.c_void_p()
     assert L.qs_alloc(0, 1, None, None, C.byref(h)) == Q.QS_EINVAL

@@ -519,10 +519,11 @@ def test_arith_equals_the_cuccaro_networks_on_every_input(O, S, m, kind):
     aq, bq, cq, anc = S.arith_layout(m)
     psi = np.zeros(1 << (3 * m + 1), dtype=np.complex128)
     psi[:1 << (3 * m)] = S.normal_state(3 * m, 30 + m)
-    net = (S.mul_gate_circuit_on if kind == 0 else S.div_gate_circuit_on)(aq, bq, cq, anc)
-    assert all(len(g.targets) <= 2 for g in net)
-    ref = O.apply_circuit(psi, net)
-    assert np.array_equal(O.arith(psi, kind, 0, m, 2 * m, m), ref)
+    for qa, qb, qc in ((aq, bq, cq), (cq, aq, bq)):
+        net = (S.mul_gate_circuit_on if kind == 0 else S.div_gate_circuit_on)(qa, qb, qc, anc)
+        assert all(len(g.targets) <= 2 for g in net)
+        ref = O.apply_circuit(psi, net)
+        assert np.array_equal(O.arith(psi, kind, qa[0], qb[0], qc[0], m), ref)
 
 
 def test_arith_gate_counts(S):
