@@ -301,6 +301,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain part")
     ap.add_argument("--no-qpe", action="store_true", help="skip the phase-estimation part")
     ap.add_argument("--no-arith", action="store_true", help="skip the multiplication/division part")
+    ap.add_argument("--arith-ms", default="4,6,8,10", help="register widths m of the multiplication/division part")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state-vector path is not sharded "
@@ -319,7 +320,8 @@ def main():
         print(json.dumps({"parts": "qpe", "phase_estimation": qpe_table(Q, S)}), flush=True)
         return
     if args.parts == "arith":
-        print(json.dumps({"parts": "arith", "arithmetic": arith_table(Q, S)}), flush=True)
+        ms = tuple(int(v) for v in args.arith_ms.split(","))
+        print(json.dumps({"parts": "arith", "arithmetic": arith_table(Q, S, ms)}), flush=True)
         return
     stream = torch.cuda.Stream()  # default priority
     n = N_QUBITS
@@ -456,7 +458,7 @@ def main():
         qpe = qpe_table(Q, S)
     arith = None
     if not args.no_arith and parts_all:
-        arith = arith_table(Q, S)
+        arith = arith_table(Q, S, tuple(int(v) for v in args.arith_ms.split(",")))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) starts")
