@@ -308,16 +308,29 @@ struct TileThread {
     }
 };
 
-// Load a tile straight into LDS.
+// Load a tile into LDS. Loads go out in batches of 8 into registers before
+// any is written to LDS, so a thread has up to 8 reads in flight instead of
+// waiting for each one.
 template <typename R, int NT>
 __device__ void tile_load(const typename V2<R>::T *__restrict__ src, const PassArgs &pa, uint64_t base,
                           const TileLds<typename V2<R>::T> &T, const TileThread &th)
 {
-    const typename V2<R>::T *s0 = src + (base | tile_colbits(pa, th.c0));
+    using C2 = typename V2<R>::T;
+    constexpr int B = 8;
+    const C2 *s0 = src + (base | tile_colbits(pa, th.c0));
     const int L = 1 << pa.r;
-    for (int i = 0; i < th.reps; ++i) {
-        const int l = th.l0 + i * th.lstep;
-        if (l < L) T.tile[phys(th.c0, l, T.S)] = load_amp(s0 + (uint64_t(l) << pa.dig_lo), pa.nt);
+    for (int i0 = 0; i0 < th.reps; i0 += B) {
+        C2 v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int l = th.l0 + (i0 + k) * th.lstep;
+            if (i0 + k < th.reps && l < L) v[k] = load_amp(s0 + (uint64_t(l) << pa.dig_lo), pa.nt);
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int l = th.l0 + (i0 + k) * th.lstep;
+            if (i0 + k < th.reps && l < L) T.tile[phys(th.c0, l, T.S)] = v[k];
+        }
     }
 }
 
