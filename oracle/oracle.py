@@ -372,6 +372,28 @@ def qpe_powers(psi, gates, ctrl_lo, b):
     return psi
 
 
+def qpe_eig_powers(psi, gates, m, ctrl_lo, b):
+    """The same controlled powers by the eigensolver route of Sec. III-C:
+    U = V diag(e^(i theta)) V^(-1) from numpy.linalg.eig of U's dense matrix
+    (block_matrix); the slice of psi whose control register (qubits
+    ctrl_lo .. ctrl_lo+b-1) holds c gets V diag(e^(i c theta)) V^(-1). The
+    target register is qubits 0 .. m-1."""
+    psi = _c128(psi).copy()
+    n = _nq(psi)
+    U = block_matrix(m, gates)
+    w, V = np.linalg.eig(U)
+    Vi = np.linalg.inv(V)
+    theta = np.angle(w)
+    X = psi.reshape(-1, 1 << m).T                    # column j: target amplitudes of the other bits j
+    cols = np.arange(X.shape[1])
+    c = (cols >> (ctrl_lo - m)) & ((1 << b) - 1)
+    Y = Vi @ X
+    Y *= np.exp(1j * np.outer(theta, c))
+    out = (V @ Y).T.reshape(-1)
+    assert out.size == 1 << n
+    return out
+
+
 def dft_numpy(psi, q_lo=0, m=None, inverse=False):
     """Independent library check of the QFT formula: ifft with orthonormal
     scaling has the +2 pi i sign of Sec. III-B; fft is its inverse."""

@@ -534,3 +534,28 @@ def test_arith_gate_counts(S):
         aq, bq, cq, anc = S.arith_layout(m)
         assert len(S.mul_gate_circuit_on(aq, bq, cq, anc)) == 3 * m * (m + 1)
         assert len(S.div_gate_circuit_on(aq, bq, cq, anc)) == m * (12 * m + 2)
+
+
+@pytest.mark.parametrize("m,b,n", [(2, 3, 5), (3, 3, 7), (3, 2, 8)])
+def test_qpe_eig_route_equals_gate_level_powers(O, S, m, b, n):
+    """The eigensolver route (numpy.linalg.eig of the dense U) gives the
+    same state as running the gate list 2^j times per control qubit, also
+    with a spectator qubit above the control register."""
+    rng = np.random.default_rng(40 + m)
+    gates = [S.Gate((q,), S.haar_2x2(rng)) for q in range(m)] + [S.cnot(0, m - 1), S.cz(0, 1)]
+    psi = S.normal_state(n, 6 + m)
+    ref = O.qpe_powers(psi, gates, m, b)
+    assert np.abs(O.qpe_eig_powers(psi, gates, m, m, b) - ref).max() < 1e-12
+
+
+def test_qpe_eig_route_phase_kickback(O, S):
+    """A diagonal U with eigenphase 2 pi k / 2^b on |1..1>: after the powers
+    the control register of the eigenstate holds e^(2 pi i k c / 2^b)."""
+    m, b, k = 2, 4, 5
+    th = 2 * np.pi * k / 2 ** b
+    gates = [S.Gate((1, 0), np.diag([1, 1, 1, np.exp(1j * th)]))]
+    psi = np.zeros(1 << (m + b), dtype=np.complex128)
+    psi[3 + 4 * np.arange(1 << b)] = 2 ** (-b / 2)
+    out = O.qpe_eig_powers(psi, gates, m, m, b)
+    c = np.arange(1 << b)
+    assert np.abs(out[3 + 4 * c] - np.exp(1j * th * c) * 2 ** (-b / 2)).max() < 1e-13
