@@ -143,11 +143,11 @@ def qpe_table(Q, S, ms=(8, 9, 10, 11, 12, 13, 14)):
     """Phase estimation of a 1D transverse-field Ising Trotter step (4m-3
     gates) on m qubits, the example of Table 2, timed on this GPU:
     applying controlled U once to an (m+1)-qubit state,
-    building the dense U, one FP64 squaring; the crossover precision follows
-    from the rule behind Table 2. Then one whole b-bit estimate both ways at
+    building the dense U, one FP64 squaring, the eigendecomposition; the
+    crossover precisions follow from the rule behind Table 2. Then one whole b-bit estimate both ways at
     m = 10, b = 10 (state of 20 qubits): the controlled powers simulated
-    (2^b - 1 runs of U) against the emulated ones, each followed by the
-    emulated inverse QFT. Simulation runs U as a program fused into blocks of
+    (2^b - 1 runs of U) against the emulated ones (squaring, and the
+    eigensolver route), each followed by the emulated inverse QFT. Simulation runs U as a program fused into blocks of
     up to 4 qubits, the simulator's fastest form."""
     import torch
     out = {"unit": "ms", "rows": []}
@@ -178,11 +178,16 @@ def qpe_table(Q, S, ms=(8, 9, 10, 11, 12, 13, 14)):
         u = Q.Unitary(gates, m, 4, stream=stream.cuda_stream)
         t_sq = timed(u.square, reps=2)
         u.free()
+        u = Q.Unitary(gates, m, 4, stream=stream.cuda_stream)
+        t_eig = timed(u.eig, reps=1)
+        u.free()
         torch.cuda.empty_cache()
         out["rows"].append({"m": m, "gates": len(gates), "t_apply_ms": round(t_apply, 4),
                             "t_build_ms": round(t_build, 4), "t_square_ms": round(t_sq, 4),
-                            "crossover_bits_squaring": Q.qpe_crossover_bits(t_apply, t_build, t_sq, True)})
-        log("qpe m=%d: apply %.3f ms, build %.3f ms, square %.3f ms" % (m, t_apply, t_build, t_sq))
+                            "t_eig_ms": round(t_eig, 3),
+                            "crossover_bits_squaring": Q.qpe_crossover_bits(t_apply, t_build, t_sq, True),
+                            "crossover_bits_eig": Q.qpe_crossover_bits(t_apply, t_build, t_eig, False)})
+        log("qpe m=%d: apply %.3f ms, build %.3f ms, square %.3f ms, eig %.1f ms" % (m, t_apply, t_build, t_sq, t_eig))
     m, b = 10, 10
     gates = S.tfim_trotter_step(m)
     n = m + b
@@ -192,7 +197,13 @@ def qpe_table(Q, S, ms=(8, 9, 10, 11, 12, 13, 14)):
         st = Q.State(n, Q.QS_C128, stream=stream.cuda_stream)
         st.set(np.kron(np.ones(1 << b) / 2 ** (b / 2), psi))   # Hadamards on the control register
         t0 = time.perf_counter()
-        if emulate:
+        if emulate == "eig":
+            u = Q.Unitary(gates, m, 4, stream=stream.cuda_stream)
+            u.eig()
+            u.apply_qpe_eig(st, m, b)
+            st.sync()
+            u.free()
+        elif emulate:
             Q.emulate_qpe_powers(st, gates, m, m, b)
         else:
             for j in range(b):
@@ -210,12 +221,16 @@ def qpe_table(Q, S, ms=(8, 9, 10, 11, 12, 13, 14)):
 
     run(False)                       # warm-up: library handles, code objects
     run(True)
+    run("eig")
     t_gate, p_gate = run(False)
     t_emu, p_emu = run(True)
+    t_eig, p_eig = run("eig")
     out["estimate"] = {"m": m, "b": b, "simulated_ms": round(t_gate, 2), "emulated_ms": round(t_emu, 2),
-                       "speedup": round(t_gate / t_emu, 1),
-                       "max_abs_diff_phase_distribution": float(np.abs(p_gate - p_emu).max())}
-    log("qpe estimate m=%d b=%d: simulated %.1f ms, emulated %.1f ms" % (m, b, t_gate, t_emu))
+                       "emulated_eig_ms": round(t_eig, 2), "speedup": round(t_gate / t_emu, 1),
+                       "max_abs_diff_phase_distribution": float(np.abs(p_gate - p_emu).max()),
+                       "max_abs_diff_phase_distribution_eig": float(np.abs(p_gate - p_eig).max())}
+    log("qpe estimate m=%d b=%d: simulated %.1f ms, emulated %.1f ms (squaring) / %.1f ms (eigensolver)"
+        % (m, b, t_gate, t_emu, t_eig))
     return out
 
 

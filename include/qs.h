@@ -443,6 +443,32 @@ int qs_unitary_free(qs_unitary u);
  * caller's. */
 int qs_emulate_qpe_powers(qs_handle h, const qs_circuit *c, int m, int ctrl_lo, int b, int max_k);
 
+/* The eigensolver route of Sec. III-C: U = V diag(e^(i theta)) V^dagger,
+ * after which every controlled power costs the same. The library's
+ * eigensolver is Hermitian (rocSOLVER zheevd), so it is given
+ * H = (U + U^dagger)/2 + beta (U - U^dagger)/(2i), beta = 0.4011..., which
+ * has U's eigenvectors; each pair of neighbouring eigenvectors is then
+ * rotated by the exact eigenvectors of its 2 x 2 block of V^dagger U V (even
+ * pairs, then odd pairs), which separates eigenphases that H's eigenvalues
+ * cos(theta) + beta sin(theta) confuse (mirror images about atan(beta)); a
+ * cluster of three or more such phases is resolved only pairwise. theta_k is
+ * the argument of the final diagonal, in (-pi, pi]. Device memory: three
+ * more 2^m x 2^m matrices during the call, V kept. Synchronous; QS_EDEVICE
+ * if the eigensolver does not converge. */
+int qs_unitary_eig(qs_unitary u);
+/* Copy the eigenphases (2^m doubles) and/or V (2^m x 2^m complex128,
+ * row-major as qs_unitary_get; column k belongs to theta_k); either pointer
+ * may be NULL. QS_EINVAL before qs_unitary_eig. */
+int qs_unitary_eig_get(qs_unitary u, double *host_theta, double *host_v);
+/* All b controlled powers at once: the amplitudes whose control register
+ * (qubits [ctrl_lo, ctrl_lo + b), above qubit m - 1) holds c get
+ * U^c = V diag(e^(i c theta)) V^dagger on qubits [0, m): two GEMMs over the
+ * state viewed as a 2^m x 2^(n-m) matrix (FP64, or FP32 with V rounded once
+ * for complex64 states) around one elementwise phase computed in FP64. The
+ * same result as qs_emulate_qpe_powers up to rounding. Uses the scratch
+ * state; the result is written back in place. */
+int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
+
 /* ---------------------------------------------------------------------- */
 /* Launch-parameter table (filled by an autotuner, read by the dispatchers) */
 /* ---------------------------------------------------------------------- */

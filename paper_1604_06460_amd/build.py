@@ -48,7 +48,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + \
-        ["-L/opt/rocm/lib", "-lrocblas"]
+        ["-L/opt/rocm/lib", "-lrocblas", "-lrocsolver"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

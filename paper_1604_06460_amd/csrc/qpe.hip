@@ -16,9 +16,23 @@
 // set come in runs of 2^(q-m) every 2^(q-m+1): one strided-batched GEMM
 // computes U times every run into the second buffer, a copy kernel moves the
 // other half, and the buffers swap.
+//
+// The eigensolver route: U = V diag(e^(i theta)) V^dagger. The library's
+// eigensolvers are Hermitian, so they are given H = (U + U^dagger)/2 +
+// beta (U - U^dagger)/(2i): it shares U's eigenvectors (U is normal) and its
+// eigenvalues cos(theta) + beta sin(theta) separate distinct eigenphases
+// unless two of them are mirror images about atan(beta). Such near-collisions
+// could mix a pair of eigenvectors, so V^dagger U V is formed (two GEMMs)
+// and each pair of neighbouring columns (even pairs, then odd pairs) is
+// rotated by the exact eigenvectors of its 2 x 2 block. The eigenphases are
+// the arguments of the final diagonal. Every controlled power then comes at
+// once: the slice of the state whose control register holds c gets
+// V diag(e^(i c theta)) V^dagger, two GEMMs over the state viewed as a
+// 2^m x 2^(n-m) matrix and one elementwise phase.
 #include "qs_internal.h"
 
 #include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <cstring>
@@ -32,6 +46,11 @@ struct qs_unitary_t {
     double *tmp = nullptr;   // squaring target
     float *u32 = nullptr;    // complex64 copy for complex64 states (refreshed on demand)
     bool u32_valid = false;
+    double *v = nullptr;     // eigenvectors (column-major), after qs_unitary_eig
+    double *theta = nullptr; // eigenphases in (-pi, pi]
+    float *v32 = nullptr;    // complex64 copy of v
+    bool v32_valid = false;
+    bool eig_valid = false;
     size_t dim() const { return size_t(1) << m; }
     size_t elems() const { return dim() * dim(); }
 };
@@ -89,6 +108,108 @@ __global__ void k_transpose(const double2 *__restrict__ src, double2 *__restrict
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
          i += uint64_t(gridDim.x) * blockDim.x)
         dst[(i & (d - 1)) * d + (i >> m)] = src[i];
+}
+
+// H = (U + U^dagger)/2 + beta (U - U^dagger)/(2i), column-major
+__global__ void k_herm_blend(const double2 *__restrict__ U, double2 *__restrict__ H, int m, double beta)
+{
+    const uint64_t d = 1ull << m, count = d * d;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t r = i & (d - 1), c = i >> m;
+        const double2 a = U[i], t = U[r * d + c];          // U[r][c], U[c][r]
+        const double sx = 0.5 * (a.x + t.x), sy = 0.5 * (a.y - t.y);   // (a + conj t)/2
+        const double dx = 0.5 * (a.x - t.x), dy = 0.5 * (a.y + t.y);   // (a - conj t)/2
+        H[i] = double2{sx + beta * dy, sy - beta * dx};                // + beta * (a - conj t)/(2i)
+    }
+}
+
+__device__ __forceinline__ double2 cm(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return double2{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double2 csqrt(double2 z)
+{
+    const double r = sqrt(sqrt(cabs2(z)));
+    const double ph = 0.5 * atan2(z.y, z.x);
+    return double2{r * cos(ph), r * sin(ph)};
+}
+
+// Pair p (columns k = 2p + parity and k + 1): the unitary Q whose first column
+// is the eigenvector of the 2 x 2 block of D = V^dagger U V for the eigenvalue
+// nearer D[k][k] (the second column is its orthogonal complement, the other
+// eigenvector of a normal block); the identity for a scalar block.
+__global__ void k_pair_q(const double2 *__restrict__ D, double2 *__restrict__ Q, int m, int parity)
+{
+    const uint64_t d = 1ull << m;
+    const uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t k = 2 * p + uint64_t(parity);
+    if (k + 1 >= d) return;
+    const double2 a = D[k + k * d], b = D[k + (k + 1) * d], c = D[(k + 1) + k * d], e = D[(k + 1) + (k + 1) * d];
+    const double2 h = double2{0.5 * (a.x - e.x), 0.5 * (a.y - e.y)};
+    const double2 disc = csqrt(double2{h.x * h.x - h.y * h.y + (b.x * c.x - b.y * c.y),
+                                       2 * h.x * h.y + (b.x * c.y + b.y * c.x)});
+    const double2 mid = double2{0.5 * (a.x + e.x), 0.5 * (a.y + e.y)};
+    double2 mu = double2{mid.x + disc.x, mid.y + disc.y};
+    const double2 mu2 = double2{mid.x - disc.x, mid.y - disc.y};
+    if (cabs2(csub(mu2, a)) < cabs2(csub(mu, a))) mu = mu2;
+    double2 x = b, y = csub(mu, a);                              // (B - mu) v = 0, first row
+    const double2 x2 = csub(mu, e), y2 = c;                      // second row
+    if (cabs2(x2) + cabs2(y2) > cabs2(x) + cabs2(y)) { x = x2; y = y2; }
+    const double nrm = sqrt(cabs2(x) + cabs2(y));
+    const double scale = sqrt(cabs2(a) + cabs2(e)) + 1e-300;
+    double2 *q = Q + 4 * p;
+    if (nrm < 1e-13 * scale) {
+        q[0] = double2{1, 0}; q[1] = double2{0, 0}; q[2] = double2{0, 0}; q[3] = double2{1, 0};
+        return;
+    }
+    x = double2{x.x / nrm, x.y / nrm};
+    y = double2{y.x / nrm, y.y / nrm};
+    q[0] = x;                                   // Q[0][0]
+    q[1] = y;                                   // Q[1][0]
+    q[2] = double2{-y.x, y.y};                  // Q[0][1] = -conj(y)
+    q[3] = double2{x.x, -x.y};                  // Q[1][1] = conj(x)
+}
+
+// V[:, k..k+1] <- V[:, k..k+1] Q for every pair
+__global__ void k_pair_apply(double2 *__restrict__ V, const double2 *__restrict__ Q, int m, int parity)
+{
+    const uint64_t d = 1ull << m, npairs = (d - uint64_t(parity)) / 2, count = npairs * d;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t r = i & (d - 1), p = i >> m, k = 2 * p + uint64_t(parity);
+        const double2 *q = Q + 4 * p;
+        const double2 v0 = V[r + k * d], v1 = V[r + (k + 1) * d];
+        const double2 a = cm(v0, q[0]), b = cm(v1, q[1]), c = cm(v0, q[2]), e = cm(v1, q[3]);
+        V[r + k * d] = double2{a.x + b.x, a.y + b.y};
+        V[r + (k + 1) * d] = double2{c.x + e.x, c.y + e.y};
+    }
+}
+
+__global__ void k_diag_arg(const double2 *__restrict__ D, double *__restrict__ theta, int m)
+{
+    const uint64_t d = 1ull << m;
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < d; k += uint64_t(gridDim.x) * blockDim.x) {
+        const double2 z = D[k + k * d];
+        theta[k] = atan2(z.y, z.x);
+    }
+}
+
+// Y[i] *= exp(i c theta_k): k = target index (low m bits of i), c = the
+// control register value of column i >> m
+template <typename C2, typename R>
+__global__ void k_eig_phase(C2 *__restrict__ Y, const double *__restrict__ theta, int m, int cshift, int b,
+                            uint64_t col0, uint64_t count)
+{
+    const uint64_t cmask = (1ull << b) - 1;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t k = i & ((1ull << m) - 1), col = col0 + (i >> m);
+        const double c = double((col >> cshift) & cmask);
+        double sn, cs;
+        sincos(c * theta[k], &sn, &cs);
+        const C2 y = Y[i];
+        Y[i] = C2{R(double(y.x) * cs - double(y.y) * sn), R(double(y.x) * sn + double(y.y) * cs)};
+    }
 }
 
 unsigned grid_of(uint64_t items)
@@ -265,7 +386,174 @@ int qs_unitary_free(qs_unitary u)
     if (u->u) (void)hipFree(u->u);
     if (u->tmp) (void)hipFree(u->tmp);
     if (u->u32) (void)hipFree(u->u32);
+    if (u->v) (void)hipFree(u->v);
+    if (u->theta) (void)hipFree(u->theta);
+    if (u->v32) (void)hipFree(u->v32);
     delete u;
+    return QS_OK;
+}
+
+int qs_unitary_eig(qs_unitary u)
+{
+    clear_error();
+    if (!u) return fail(QS_EINVAL, "NULL unitary");
+    int rc = QS_OK;
+    rocblas_handle bl = blas(rc);
+    if (rc) return rc;
+    const size_t d = u->dim(), bytes = u->elems() * 16;
+    if (!u->v) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->v), bytes));
+    if (!u->theta) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->theta), d * sizeof(double)));
+    if (!u->tmp) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->tmp), bytes));
+    double2 *D = nullptr, *Q = nullptr;
+    double *lam = nullptr, *work = nullptr;
+    rocblas_int *info = nullptr;
+    auto cleanup = [&](int r) {
+        if (D) (void)hipFree(D);
+        if (Q) (void)hipFree(Q);
+        if (lam) (void)hipFree(lam);
+        if (work) (void)hipFree(work);
+        if (info) (void)hipFree(info);
+        return r;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(reinterpret_cast<void **>(&D), bytes)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&Q), (d / 2 + 1) * 4 * sizeof(double2))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&lam), d * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&work), d * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&info), sizeof(rocblas_int))) != hipSuccess)
+        return cleanup(hip_fail(e, "hipMalloc(eigendecomposition)"));
+    if ((rc = blas_check(rocblas_set_stream(bl, u->stream), "rocblas_set_stream"))) return cleanup(rc);
+    const double beta = 0.4011269376164746;   // tan(0.38196...): mirror axis of no special phase
+    double2 *V = reinterpret_cast<double2 *>(u->v);
+    hipLaunchKernelGGL(k_herm_blend, dim3(grid_of(u->elems())), dim3(256), 0, u->stream,
+                       reinterpret_cast<const double2 *>(u->u), V, u->m, beta);
+    if ((e = hipGetLastError()) != hipSuccess) return cleanup(hip_fail(e, "k_herm_blend"));
+    const rocblas_int n = rocblas_int(d);
+    if ((rc = blas_check(rocsolver_zheevd(bl, rocblas_evect_original, rocblas_fill_lower, n,
+                                          reinterpret_cast<rocblas_double_complex *>(V), n, lam, work, info),
+                         "rocsolver_zheevd")))
+        return cleanup(rc);
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    const auto *Ud = reinterpret_cast<const rocblas_double_complex *>(u->u);
+    auto *Vd = reinterpret_cast<rocblas_double_complex *>(V);
+    auto *W = reinterpret_cast<rocblas_double_complex *>(u->tmp);
+    auto *Dd = reinterpret_cast<rocblas_double_complex *>(D);
+    auto form_d = [&]() {   // D = V^dagger (U V)
+        int r = blas_check(rocblas_zgemm(bl, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, Ud, n,
+                                         Vd, n, &zero, W, n),
+                           "rocblas_zgemm");
+        if (!r)
+            r = blas_check(rocblas_zgemm(bl, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, n, n,
+                                         &one, Vd, n, W, n, &zero, Dd, n),
+                           "rocblas_zgemm");
+        return r;
+    };
+    if ((rc = form_d())) return cleanup(rc);
+    for (int parity = 0; parity < 2 && d >= 2; ++parity) {
+        const uint64_t npairs = (d - uint64_t(parity)) / 2;
+        if (npairs == 0) continue;
+        hipLaunchKernelGGL(k_pair_q, dim3(unsigned((npairs + 255) / 256)), dim3(256), 0, u->stream, D, Q, u->m,
+                           parity);
+        hipLaunchKernelGGL(k_pair_apply, dim3(grid_of(npairs * d)), dim3(256), 0, u->stream, V, Q, u->m, parity);
+        if ((e = hipGetLastError()) != hipSuccess) return cleanup(hip_fail(e, "pair rotation"));
+        if ((rc = form_d())) return cleanup(rc);
+    }
+    hipLaunchKernelGGL(k_diag_arg, dim3(grid_of(d)), dim3(256), 0, u->stream, D, u->theta, u->m);
+    rocblas_int hinfo = 0;
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, u->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(u->stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "eigendecomposition"));
+    if (hinfo != 0) return cleanup(fail(QS_EDEVICE, "rocsolver_zheevd did not converge (info %d)", int(hinfo)));
+    u->eig_valid = true;
+    u->v32_valid = false;
+    return cleanup(QS_OK);
+}
+
+int qs_unitary_eig_get(qs_unitary u, double *host_theta, double *host_v)
+{
+    clear_error();
+    if (!u) return fail(QS_EINVAL, "NULL unitary");
+    if (!u->eig_valid) return fail(QS_EINVAL, "no eigendecomposition: call qs_unitary_eig first");
+    if (host_theta)
+        QS_HIP(hipMemcpyAsync(host_theta, u->theta, u->dim() * sizeof(double), hipMemcpyDeviceToHost, u->stream));
+    if (host_v) {
+        hipLaunchKernelGGL(k_transpose, dim3(grid_of(u->elems())), dim3(256), 0, u->stream,
+                           reinterpret_cast<const double2 *>(u->v), reinterpret_cast<double2 *>(u->tmp), u->m);
+        QS_HIP(hipGetLastError());
+        QS_HIP(hipMemcpyAsync(host_v, u->tmp, u->elems() * 16, hipMemcpyDeviceToHost, u->stream));
+    }
+    QS_HIP(hipStreamSynchronize(u->stream));
+    return QS_OK;
+}
+
+int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b)
+{
+    clear_error();
+    if (!h || !u) return fail(QS_EINVAL, "NULL argument");
+    if (!u->eig_valid) return fail(QS_EINVAL, "no eigendecomposition: call qs_unitary_eig first");
+    const int m = u->m;
+    if (m > h->n) return fail(QS_EINVAL, "the %d-qubit unitary does not fit the %d-qubit state", m, h->n);
+    if (b < 1 || b > 62 || ctrl_lo < m || ctrl_lo + b > h->n)
+        return fail(QS_EINVAL, "control register [%d, %d) must lie in [%d, %d)", ctrl_lo, ctrl_lo + b, m, h->n);
+    int rc = QS_OK;
+    rocblas_handle bl = blas(rc);
+    if (rc) return rc;
+    if ((rc = ensure_scratch(h))) return rc;
+    if (u->stream != h->stream) QS_HIP(hipStreamSynchronize(u->stream));
+    if ((rc = blas_check(rocblas_set_stream(bl, h->stream), "rocblas_set_stream"))) return rc;
+    const rocblas_int d = rocblas_int(1) << m;
+    const uint64_t ncols = h->dim() >> m;
+    const uint64_t chunk = std::min<uint64_t>(ncols, 1ull << 30);      // 32-bit BLAS sizes
+    const int cshift = ctrl_lo - m;
+    if (h->dtype == QS_C128) {
+        const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+        const auto *V = reinterpret_cast<const rocblas_double_complex *>(u->v);
+        for (uint64_t c0 = 0; c0 < ncols; c0 += chunk) {
+            auto *X = reinterpret_cast<rocblas_double_complex *>(h->psi) + c0 * uint64_t(d);
+            auto *Y = reinterpret_cast<rocblas_double_complex *>(h->scratch) + c0 * uint64_t(d);
+            const rocblas_int nc = rocblas_int(std::min(chunk, ncols - c0));
+            if ((rc = blas_check(rocblas_zgemm(bl, rocblas_operation_conjugate_transpose, rocblas_operation_none, d, nc,
+                                               d, &one, V, d, X, d, &zero, Y, d),
+                                 "rocblas_zgemm")))
+                return rc;
+            const uint64_t cnt = uint64_t(nc) * uint64_t(d);
+            hipLaunchKernelGGL((k_eig_phase<double2, double>), dim3(grid_of(cnt)), dim3(256), 0, h->stream,
+                               reinterpret_cast<double2 *>(Y), u->theta, m, cshift, b, c0, cnt);
+            QS_HIP(hipGetLastError());
+            if ((rc = blas_check(rocblas_zgemm(bl, rocblas_operation_none, rocblas_operation_none, d, nc, d, &one, V, d,
+                                               Y, d, &zero, X, d),
+                                 "rocblas_zgemm")))
+                return rc;
+        }
+    } else {
+        if (!u->v32) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->v32), u->elems() * 8));
+        if (!u->v32_valid) {
+            hipLaunchKernelGGL(k_cast_u, dim3(grid_of(2 * u->elems())), dim3(256), 0, h->stream, u->v, u->v32,
+                               uint64_t(2 * u->elems()));
+            QS_HIP(hipGetLastError());
+            u->v32_valid = true;
+        }
+        const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
+        const auto *V = reinterpret_cast<const rocblas_float_complex *>(u->v32);
+        for (uint64_t c0 = 0; c0 < ncols; c0 += chunk) {
+            auto *X = reinterpret_cast<rocblas_float_complex *>(h->psi) + c0 * uint64_t(d);
+            auto *Y = reinterpret_cast<rocblas_float_complex *>(h->scratch) + c0 * uint64_t(d);
+            const rocblas_int nc = rocblas_int(std::min(chunk, ncols - c0));
+            if ((rc = blas_check(rocblas_cgemm(bl, rocblas_operation_conjugate_transpose, rocblas_operation_none, d, nc,
+                                               d, &one, V, d, X, d, &zero, Y, d),
+                                 "rocblas_cgemm")))
+                return rc;
+            const uint64_t cnt = uint64_t(nc) * uint64_t(d);
+            hipLaunchKernelGGL((k_eig_phase<float2, float>), dim3(grid_of(cnt)), dim3(256), 0, h->stream,
+                               reinterpret_cast<float2 *>(Y), u->theta, m, cshift, b, c0, cnt);
+            QS_HIP(hipGetLastError());
+            if ((rc = blas_check(rocblas_cgemm(bl, rocblas_operation_none, rocblas_operation_none, d, nc, d, &one, V, d,
+                                               Y, d, &zero, X, d),
+                                 "rocblas_cgemm")))
+                return rc;
+        }
+    }
     return QS_OK;
 }
 

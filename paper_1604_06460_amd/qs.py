@@ -579,6 +579,9 @@ _sig("qs_unitary_get", [_P, _P])
 _sig("qs_apply_controlled_unitary", [_P, _P, _I])
 _sig("qs_unitary_free", [_P])
 _sig("qs_emulate_qpe_powers", [_P, C.POINTER(Circuit), _I, _I, _I, _I])
+_sig("qs_unitary_eig", [_P])
+_sig("qs_unitary_eig_get", [_P, _P, _P])
+_sig("qs_apply_qpe_eig", [_P, _P, _I, _I])
 
 
 class Unitary:
@@ -602,6 +605,22 @@ class Unitary:
 
     def apply_controlled(self, state, ctrl):
         _chk(_L.qs_apply_controlled_unitary(state.handle, self._h, int(ctrl)))
+
+    def eig(self):
+        """Eigendecomposition U = V diag(e^(i theta)) V^dagger on the device."""
+        _chk(_L.qs_unitary_eig(self._h))
+
+    def eig_get(self):
+        """(theta, V): eigenphases and eigenvectors (columns) on the host."""
+        d = 1 << self.m
+        th = np.empty(d)
+        v = np.empty((d, d), dtype=np.complex128)
+        _chk(_L.qs_unitary_eig_get(self._h, _ptr(th), _ptr(v)))
+        return th, v
+
+    def apply_qpe_eig(self, state, ctrl_lo, b):
+        """Every controlled power U^c at once (c = control register value)."""
+        _chk(_L.qs_apply_qpe_eig(state.handle, self._h, int(ctrl_lo), int(b)))
 
     def free(self):
         if self._h:

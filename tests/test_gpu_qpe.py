@@ -87,3 +87,110 @@ def test_unitary_rejects_gates_outside_the_register(Q, S):
         Q.Unitary([S.g1(S.MAT_H, 3)], 3)
     with pytest.raises(Q.QSError):
         Q.Unitary([S.mcx([4], 0)], 3)
+
+
+# ---------------------------------------------------------------------------
+# The eigensolver route
+# ---------------------------------------------------------------------------
+BETA = 0.4011269376164746        # the Hermitian blend's beta (qs_unitary_eig)
+
+
+def _check_eig(u, U, tol=1e-10):
+    th, V = u.eig_get()
+    d = U.shape[0]
+    assert np.abs(V.conj().T @ V - np.eye(d)).max() < tol
+    assert np.abs((V * np.exp(1j * th)) @ V.conj().T - U).max() < tol
+    w = np.linalg.eigvals(U)
+    assert max(np.abs(np.exp(1j * th) - x).min() for x in w) < tol
+    assert np.all(th > -np.pi - 1e-12) and np.all(th <= np.pi + 1e-12)
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 6, 8])
+def test_eig_reconstructs_the_unitary(Q, O, S, m):
+    gates = S.tfim_trotter_step(m, dt=0.4) if m > 1 else _circuit(S, 1, 5)
+    U = O.block_matrix(m, gates)
+    u = Q.Unitary(gates, m)
+    u.eig()
+    _check_eig(u, U)
+    u.free()
+
+
+def test_eig_separates_phases_the_hermitian_blend_confuses(Q, O, S):
+    """Eigenphases in pairs mirrored about atan(beta): the blend's eigenvalues
+    cos + beta sin coincide within each pair (and two exact degeneracies of U
+    itself), so only the pair rotations recover U's eigenvectors."""
+    m, d = 4, 16
+    phi = np.arctan(BETA)
+    rng = np.random.default_rng(12)
+    delta = rng.uniform(0.1, 1.4, d // 2 - 1)
+    th = np.concatenate([phi + delta, phi - delta, [0.3, 0.3]])
+    q, r = np.linalg.qr(rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+    M = (q * np.exp(1j * th)) @ q.conj().T
+    gates = [S.Gate(tuple(range(m)), M)]
+    U = O.block_matrix(m, gates)
+    u = Q.Unitary(gates, m)
+    u.eig()
+    _check_eig(u, U, 1e-9)
+    psi0 = S.normal_state(m + 3, 2)
+    st = Q.State(m + 3, Q.QS_C128)
+    st.set(psi0)
+    u.apply_qpe_eig(st, m, 3)
+    assert np.abs(st.get() - O.qpe_powers(psi0, gates, m, 3)).max() < 1e-9
+    st.free()
+    u.free()
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+@pytest.mark.parametrize("m,b,n", [(4, 4, 9), (2, 5, 8), (6, 3, 10), (3, 2, 8)])
+def test_qpe_eig_equals_gate_level(Q, O, S, dtype, m, b, n):
+    """Every controlled power from the eigendecomposition against the oracle's
+    2^j runs of the gate list per control qubit (spectators above the
+    control register in the last two cases)."""
+    gates = S.tfim_trotter_step(m, dt=0.3) if m > 1 else _circuit(S, 1, 8)
+    psi0 = S.normal_state(n, 17 + m)
+    ref = O.qpe_powers(psi0, gates, m, b)
+    u = Q.Unitary(gates, m)
+    u.eig()
+    st = Q.State(n, dtype)
+    st.set(psi0)
+    u.apply_qpe_eig(st, m, b)
+    assert np.abs(st.get() - ref).max() < 10 * TOL[dtype]
+    st.free()
+    u.free()
+
+
+def test_qpe_eig_equals_squaring_route_at_10_qubits(Q, S):
+    """m = 10, b = 10 on a 22-qubit state: the two emulation routes agree."""
+    m, b, n = 10, 10, 22
+    gates = S.tfim_trotter_step(m)
+    psi0 = S.normal_state(n, 3)
+    a = Q.State(n, Q.QS_C128)
+    a.set(psi0)
+    Q.emulate_qpe_powers(a, gates, m, m, b)
+    u = Q.Unitary(gates, m)
+    u.eig()
+    e = Q.State(n, Q.QS_C128)
+    e.set(psi0)
+    u.apply_qpe_eig(e, m, b)
+    assert np.abs(a.get() - e.get()).max() < 1e-9
+    for s in (a, e):
+        s.free()
+    u.free()
+
+
+def test_qpe_eig_end_to_end_and_errors(Q, S):
+    b, k = 7, 99
+    gates = [S.Gate((0,), np.diag([1.0, np.exp(2j * np.pi * k / 2 ** b)]))]
+    u = Q.Unitary(gates, 1)
+    st = Q.State(1 + b, Q.QS_C128)
+    with pytest.raises(Q.QSError):
+        u.apply_qpe_eig(st, 1, b)                  # no eigendecomposition yet
+    u.eig()
+    with pytest.raises(Q.QSError):
+        u.apply_qpe_eig(st, 0, b)                  # control register inside U's register
+    st.apply_gates([S.g1(S.MAT_X, 0)] + [S.g1(S.MAT_H, 1 + j) for j in range(b)])
+    u.apply_qpe_eig(st, 1, b)
+    st.emulate_qft(1, b, inverse=True)
+    assert abs(abs(st.get()[(k << 1) | 1]) - 1) < 1e-12
+    st.free()
+    u.free()
