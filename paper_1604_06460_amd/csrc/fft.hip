@@ -16,15 +16,17 @@
 //
 // Inside a pass a workgroup holds a tile of 2^r digit values x C columns
 // (C consecutive values of the lowest available bits, so global accesses run
-// in C-element segments; with the whole LDS of a CU a 10-bit digit gets
-// C = 8 complex128 or 16 complex64 columns, one full 128-byte line) in LDS
-// and performs the 2^r-point DFT as radix-2^rho register stages (rho <= 4),
-// again decimation in frequency.
+// in C-element segments; the default 80 KB tile gives a 10-bit digit C = 4
+// complex128 or 8 complex64 columns, 64 bytes, and the whole LDS of a CU one
+// full 128-byte line) in LDS and performs the 2^r-point DFT as radix-2^rho
+// register stages (rho <= 3 for complex128, 4 for complex64), again
+// decimation in frequency.
 //
-// Launch: a persistent grid (as many workgroups as are co-resident) in which
-// each workgroup walks a contiguous range of tiles and prefetches the next
-// tile into registers while the current one is transformed in LDS, so HBM
-// reads stay in flight during the LDS stages and the stores. The LDS layout
+// Launch: one workgroup per tile (k_fft_pass, the default; two workgroups
+// share a CU with the 80 KB tile) in an XCD-aware order. A persistent
+// alternative (k_fft_stream, tuning option 2) walks a contiguous range of
+// tiles and prefetches the next tile into registers while the current one is
+// transformed; it needs more registers and is slower here. The LDS layout
 // is column-major with a 4-element pad per column and the low 4 bits of the
 // row XOR-swizzled by the next 4, which keeps both the strided and the
 // contiguous stage accesses free of bank conflicts.

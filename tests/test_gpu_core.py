@@ -359,3 +359,28 @@ def test_handles_after_out_of_place_ops_free_cleanly(Q, S):
     st = Q.State(12, 1)
     st.apply_gate([0], S.MAT_H)
     assert abs(st.norm2() - 1) < 1e-14
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_load_device_streaming_copy_and_fallbacks(Q, S, dtype):
+    """qs_load_device copies with the library's 16-byte streaming kernel when
+    both buffers are 16-byte aligned and falls back to the runtime copy
+    otherwise (a complex64 source one amplitude, 8 bytes, into a tensor):
+    both paths move the amplitudes bit for bit, from 2 to 2^17 amplitudes;
+    an overlapping source is rejected."""
+    import torch
+    tdt = torch.complex128 if dtype == 1 else torch.complex64
+    for n in (1, 2, 7, 17):
+        x = torch.randn((1 << n) + 1, dtype=tdt, device="cuda")
+        ref = x.cpu().numpy()
+        for off in (0, 1):                                 # aligned, then one amplitude in
+            st = Q.State(n, dtype)
+            st.load_device(x.data_ptr() + off * x.element_size())
+            got = st.get()
+            assert np.array_equal(got.view(np.uint8), ref[off:off + (1 << n)].view(np.uint8)), (n, off)
+            st.free()
+    st = Q.State(4, dtype)
+    _, _, p = st.info()
+    with pytest.raises(Q.QSError):
+        st.load_device(p)
+    st.free()
