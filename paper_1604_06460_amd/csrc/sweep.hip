@@ -342,6 +342,27 @@ __global__ __launch_bounds__(kBlock) void k_phase1(typename V2<R>::T *__restrict
     }
 }
 
+// The same phase when some pinned bits lie inside a 128-byte line: writing
+// only the selected amplitudes would leave every line partly written, which
+// the memory turns into read-modify-writes. Instead every amplitude of the
+// lines whose pinned bits above the line match is read and written back,
+// multiplied where the in-line bits match too (unchanged amplitudes are
+// stored as read, bit for bit).
+template <typename R, typename IT>
+__global__ __launch_bounds__(kBlock) void k_phase1_lines(typename V2<R>::T *__restrict__ psi, IT n_items,
+                                                         FixArgs fx, uint64_t low_mask, uint64_t low_vals, R pr,
+                                                         R pi)
+{
+    using C2 = typename V2<R>::T;
+    const IT stride = IT(gridDim.x) * kBlock;
+    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_items; g += stride) {
+        C2 *p = psi + expand<IT>(g, fx);
+        C2 a = *p;
+        if ((uint64_t(p - psi) & low_mask) == low_vals) a = C2{pr * a.x - pi * a.y, pr * a.y + pi * a.x};
+        *p = a;
+    }
+}
+
 // Diagonal gate: one elementwise pass; the entry is picked by the target
 // bits of the index. Controls are pinned as fixed bits.
 template <typename R, int K, typename IT>
@@ -667,6 +688,22 @@ int phase1_t(qs_state *h, const GateDesc &d, double pr, double pi)
     uint64_t vals = d.ctrl_vals;
     for (int m = 0; m < d.k; ++m)
         if ((d.phase_index >> m) & 1) vals |= 1ull << d.targets[m];
+    constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
+    int hi[64], nhi = 0;
+    uint64_t low_mask = 0;
+    for (int i = 0; i < np; ++i) {
+        if (pos[i] < kLineBits) low_mask |= 1ull << pos[i];
+        else hi[nhi++] = pos[i];
+    }
+    if (low_mask) {
+        uint64_t hi_vals = vals & ~low_mask;
+        if (int rc = make_fix(hi, nhi, hi_vals, fx)) return rc;
+        const IT n_items = IT(h->dim() >> nhi);
+        hipLaunchKernelGGL((k_phase1_lines<R, IT>), dim3(grid_for(n_items)), dim3(kBlock), 0, h->stream,
+                           static_cast<C2 *>(h->psi), n_items, fx, low_mask, vals & low_mask, R(pr), R(pi));
+        QS_HIP(hipGetLastError());
+        return QS_OK;
+    }
     if (int rc = make_fix(pos, np, vals, fx)) return rc;
     const IT n_items = IT(h->dim() >> np);
     hipLaunchKernelGGL((k_phase1<R, IT>), dim3(grid_for(n_items)), dim3(kBlock), 0, h->stream,

@@ -384,3 +384,33 @@ def test_load_device_streaming_copy_and_fallbacks(Q, S, dtype):
     with pytest.raises(Q.QSError):
         st.load_device(p)
     st.free()
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_structured_gates_inside_a_cache_line(Q, O, S, dtype):
+    """Phase gates whose pinned bits lie inside a 128-byte line take the
+    whole-line form (every amplitude of the touched lines read and written
+    back), and permutation gates with targets there move only what they
+    touch: same result as the oracle, permutations bit for bit."""
+    n = 12
+    psi = S.normal_state(n, 77)
+    th = 0.7
+    cases = [
+        S.cr(0, 1, th), S.cr(1, 2, th), S.cr(2, 3, th), S.cr(0, 11, th), S.cr(3, 1, th),
+        S.Gate((0,), np.diag([1, np.exp(1j * th)])),                            # phase on qubit 0
+        S.Gate((5,), np.diag([1, np.exp(1j * th)]), 0b11, 0b01),                 # controls 0 (=1), 1 (=0)
+        S.Gate((2,), np.diag([np.exp(1j * th), 1]), 1 << 9, 1 << 9),             # phase on |0> of qubit 2
+    ]
+    perms = [S.swap(0, 11), S.swap(1, 2), S.swap(3, 9), S.cnot(0, 7), S.cnot(7, 1), S.mcx((3, 8), 0)]
+    for g, is_perm in [(g, False) for g in cases] + [(g, True) for g in perms]:
+        st = Q.State(n, dtype)
+        st.set(psi)
+        before = st.get()
+        st.apply_gate(g.targets, g.matrix, g.ctrl_mask, g.ctrl_vals)
+        ref = O.apply_gate(before.astype(np.complex128), g.targets, g.matrix, g.ctrl_mask, g.ctrl_vals)
+        got = st.get()
+        if is_perm:
+            assert np.array_equal(got.view(np.uint8), ref.astype(got.dtype).view(np.uint8)), g.name
+        else:
+            assert np.abs(got - ref).max() < (1e-13 if dtype == 1 else 2e-6), g.name
+        st.free()
