@@ -171,8 +171,14 @@ typedef struct qs_circuit {
  * in order. Outputs (caller-allocated): *n_blocks; block_of_gate[n_gates];
  * block_k[n_gates] (qubit count of each block, first *n_blocks used);
  * block_qubits[n_gates * QS_MAX_K] (ascending qubits of block b at
- * b*QS_MAX_K). A gate wider than max_k forms a block of its own. Runs
- * without a GPU. */
+ * b*QS_MAX_K). A gate wider than max_k forms a block of its own. Blocks
+ * with several qubits at or above 20 (for a complex128 state their rows are
+ * 16 MiB or more apart, which the memory serves slowly) sweep more slowly,
+ * so a second plan is made in which a gate does not join a block that would
+ * then hold two such qubits (a block's first gate may bring more), and the
+ * plan with the lower estimated sweep time is returned. qs_compile does the
+ * same at the state's row size (qubit 21 for complex64). Runs without a
+ * GPU. */
 int qs_plan_fusion(const qs_circuit *c, int n_qubits, int max_k, int *n_blocks,
                    int *block_of_gate, int *block_k, int *block_qubits);
 

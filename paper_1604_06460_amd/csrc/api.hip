@@ -400,7 +400,8 @@ int qs_plan_fusion(const qs_circuit *c, int n_qubits, int max_k, int *n_blocks, 
     if (!n_blocks || (c->n_gates && (!block_of_gate || !block_k || !block_qubits)))
         return fail(QS_EINVAL, "NULL output arrays");
     Plan p;
-    if (int rc = plan_fusion(n_qubits, c->n_gates, c->k, c->targets, c->ctrl_mask, max_k, p)) return rc;
+    if (int rc = plan_fusion(n_qubits, c->n_gates, c->k, c->targets, c->ctrl_mask, max_k, p, far_qubit(16)))
+        return rc;
     *n_blocks = int(p.block_gates.size());
     for (int g = 0; g < c->n_gates; ++g) block_of_gate[g] = p.block_of_gate[size_t(g)];
     for (size_t b = 0; b < p.block_gates.size(); ++b) {
@@ -426,7 +427,8 @@ int qs_compile(qs_handle h, const qs_circuit *c, int max_k, qs_program *out)
             return fail(QS_EUNSUPPORTED, "gate %d spans more than %d qubits with its controls", g, QS_MAX_K);
     }
     Plan p;
-    if (int rc = plan_fusion(h->n, c->n_gates, c->k, c->targets, c->ctrl_mask, max_k, p)) return rc;
+    if (int rc = plan_fusion(h->n, c->n_gates, c->k, c->targets, c->ctrl_mask, max_k, p, far_qubit(h->amp_bytes())))
+        return rc;
     qs_program_t *pr = new (std::nothrow) qs_program_t();
     if (!pr) return fail(QS_ENOMEM, "host allocation failed");
     pr->n = h->n;

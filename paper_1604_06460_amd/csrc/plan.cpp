@@ -8,6 +8,17 @@
 // it. Since a joining gate shares no qubit with any gate it overtakes, the
 // two commute, and applying the blocks in order equals applying the gates in
 // order.
+//
+// Rows far apart. A block whose targets include several qubits at or above
+// far_lo has its 2^k amplitudes in rows 16 MiB or more apart that share their
+// low address bits; such sweeps run up to 1.6x slower than blocks over nearby
+// rows (the memory serves them from the same banks). A second plan is made in
+// which a gate does not join a block when it would bring a second far qubit
+// into it (it is skipped like a gate that does not fit, which keeps the order
+// argument above intact; a block's first gate may bring more), and the plan
+// with the lower estimated sweep time is kept: every block costs 1, 1.05,
+// 1.10, 1.19 or 1.30 for 0..4 far qubits (the measured busy time of 30-qubit
+// complex128 4-qubit sweeps relative to blocks without far qubits).
 #include <algorithm>
 #include <cstdint>
 #include <vector>
@@ -16,8 +27,10 @@
 
 namespace qs {
 
-int plan_fusion(int n_qubits, int n_gates, const int *k, const int *targets,
-                const uint64_t *ctrl_mask, int max_k, Plan &out)
+namespace {
+
+int plan_greedy(int n_qubits, int n_gates, const int *k, const int *targets, const uint64_t *ctrl_mask,
+                int max_k, Plan &out, int far_lo)
 {
     out.block_of_gate.assign(size_t(n_gates), -1);
     out.block_gates.clear();
@@ -31,6 +44,7 @@ int plan_fusion(int n_qubits, int n_gates, const int *k, const int *targets,
         gmask[size_t(g)] = m;
     }
     const uint64_t all = n_qubits >= 64 ? ~0ull : ((1ull << n_qubits) - 1);
+    const uint64_t far = far_lo >= 64 ? 0 : (all & ~((1ull << far_lo) - 1));
     int first = 0;
     while (first < n_gates) {
         while (first < n_gates && out.block_of_gate[size_t(first)] >= 0) ++first;
@@ -53,8 +67,10 @@ int plan_fusion(int n_qubits, int n_gates, const int *k, const int *targets,
                     blocked |= m;
                     continue;
                 }
-                if (__builtin_popcountll(q | m) <= max_k) {
-                    q |= m;
+                const uint64_t u = q | m;
+                const bool far_ok = __builtin_popcountll(u & far) <= 1 || (u & far) == (q & far);
+                if (__builtin_popcountll(u) <= max_k && far_ok) {
+                    q = u;
                     out.block_of_gate[size_t(g)] = b;
                     out.block_gates.back().push_back(g);
                 } else {
@@ -67,6 +83,31 @@ int plan_fusion(int n_qubits, int n_gates, const int *k, const int *targets,
             if ((q >> i) & 1) qs.push_back(i);
         out.block_qubits.push_back(qs);
     }
+    return QS_OK;
+}
+
+double plan_cost(const Plan &p, int far_lo)
+{
+    static const double w[] = {1.0, 1.05, 1.10, 1.19, 1.30};
+    double c = 0;
+    for (const auto &q : p.block_qubits) {
+        int f = 0;
+        for (int x : q) f += x >= far_lo;
+        c += f < 5 ? w[f] : w[4] + 0.1 * (f - 4);
+    }
+    return c;
+}
+
+}  // namespace
+
+int plan_fusion(int n_qubits, int n_gates, const int *k, const int *targets,
+                const uint64_t *ctrl_mask, int max_k, Plan &out, int far_lo)
+{
+    if (int rc = plan_greedy(n_qubits, n_gates, k, targets, ctrl_mask, max_k, out, 64)) return rc;
+    if (far_lo >= n_qubits - 1) return QS_OK;        // at most one far qubit: the plans agree
+    Plan alt;
+    if (int rc = plan_greedy(n_qubits, n_gates, k, targets, ctrl_mask, max_k, alt, far_lo)) return rc;
+    if (plan_cost(alt, far_lo) < plan_cost(out, far_lo)) out = std::move(alt);
     return QS_OK;
 }
 

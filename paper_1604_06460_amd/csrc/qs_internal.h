@@ -124,8 +124,13 @@ struct Plan {
     std::vector<std::vector<int>> block_gates;   // gate ids in circuit order
     std::vector<std::vector<int>> block_qubits;  // ascending
 };
+// far_lo: lowest qubit whose amplitude rows lie 16 MiB or more apart (bit 24
+// of the byte address); the plain greedy plan is compared with one whose
+// blocks take at most one such qubit (unless a block's first gate brings
+// more) and the cheaper kept. 64 disables the comparison.
 int plan_fusion(int n_qubits, int n_gates, const int *k, const int *targets,
-                const uint64_t *ctrl_mask, int max_k, Plan &out);
+                const uint64_t *ctrl_mask, int max_k, Plan &out, int far_lo = 64);
+inline int far_qubit(size_t amp_bytes) { return amp_bytes == 16 ? 20 : 21; }
 
 // Reductions (reduce.hip)
 int reduce_norm2(qs_state *h, double *out);
