@@ -430,12 +430,13 @@ def main():
     total_bytes = sum(bytes_part.values())
     value = total_bytes / (ms_per_step * 1e-3) / 1e9
 
-    # dominant kernel: the k=4 dense sweep (one launch per fused block)
+    # dominant kernel: the fused block sweep (one launch per block of up to
+    # k = 4 qubits; each moves the whole state once)
     sweep_ms = part_ms["fused"] / n_blocks
     achieved = 2 * amp * N / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "fused 4-qubit block sweeps (k_dense_lds<double,4> / k_dense<double,4> per the tuned "
+                "kernel": "fused block sweeps, blocks of up to 4 qubits (k_dense_lds / k_dense per the tuned "
                           "table, k_diag for diagonal blocks), average over the step's launches",
                 "avg_launch_ms": round(sweep_ms, 4), "bytes_per_launch": 2 * amp * N}
 

@@ -68,6 +68,24 @@ __device__ __forceinline__ void store_amp(C2 *p, C2 v, int nt)
     }
 }
 
+// Workgroup order over the 8 XCDs. The dispatcher hands workgroup b to XCD
+// b mod 8, so in launch order every XCD would take every eighth tile. Here
+// XCD x takes runs of C consecutive tiles (tile = run * 8C + x * C + offset),
+// which keeps each XCD on nearby addresses while all eight stay in the same
+// region of the state. Measured on 30-qubit complex128 sweeps: C = 64 for
+// the dense block sweeps and C = 128 for the elementwise gate kernels beat
+// both the launch order (6.37 -> 6.01 ms per 4-qubit block, 1015 -> 969 ms
+// for the gate-level QFT) and one contiguous eighth per XCD. Grids that are
+// not a multiple of 8C keep the launch order.
+template <typename IT, unsigned C>
+__device__ __forceinline__ IT xcd_order(unsigned b, unsigned G)
+{
+    if (G % (8 * C)) return IT(b);
+    const unsigned i = b / 8;
+    return IT(i / C) * IT(8 * C) + IT(b % 8) * IT(C) + IT(i % C);
+}
+constexpr unsigned kXcdRunDense = 64, kXcdRunElem = 128;
+
 template <typename IT>
 __device__ __forceinline__ IT expand(IT g, const FixArgs &f)
 {
@@ -130,7 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict_
     using C2 = typename V2<R>::T;
     constexpr int D = 1 << K;
     const IT stride = IT(gridDim.x) * kBlock;
-    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_groups; g += stride) {
+    const IT first = xcd_order<IT, kXcdRunDense>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    for (IT g = first; g < n_groups; g += stride) {
         C2 *p = psi + expand<IT>(g, fx);
         C2 v[D];
 #pragma unroll
@@ -181,7 +200,7 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict_
     int lp = 0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) lp |= ((lane >> b) & 1) << la.lane_pos[b];
-    for (IT t = IT(blockIdx.x); t < n_tiles; t += IT(gridDim.x)) {
+    for (IT t = xcd_order<IT, kXcdRunDense>(blockIdx.x, gridDim.x); t < n_tiles; t += IT(gridDim.x)) {
         C2 *p = psi + expand<IT>(t, fx) + lane;
         C2 v[D];
 #pragma unroll
@@ -335,7 +354,8 @@ __global__ __launch_bounds__(kBlock) void k_phase1(typename V2<R>::T *__restrict
 {
     using C2 = typename V2<R>::T;
     const IT stride = IT(gridDim.x) * kBlock;
-    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_items; g += stride) {
+    const IT first = xcd_order<IT, kXcdRunElem>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    for (IT g = first; g < n_items; g += stride) {
         C2 *p = psi + expand<IT>(g, fx);
         const C2 a = *p;
         *p = C2{pr * a.x - pi * a.y, pr * a.y + pi * a.x};
@@ -355,7 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_phase1_lines(typename V2<R>::T *__re
 {
     using C2 = typename V2<R>::T;
     const IT stride = IT(gridDim.x) * kBlock;
-    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_items; g += stride) {
+    const IT first = xcd_order<IT, kXcdRunElem>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    for (IT g = first; g < n_items; g += stride) {
         C2 *p = psi + expand<IT>(g, fx);
         C2 a = *p;
         if ((uint64_t(p - psi) & low_mask) == low_vals) a = C2{pr * a.x - pi * a.y, pr * a.y + pi * a.x};
@@ -378,7 +399,8 @@ __global__ __launch_bounds__(kBlock) void k_diag(typename V2<R>::T *__restrict__
     }
     __syncthreads();
     const IT stride = IT(gridDim.x) * kBlock;
-    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_items; g += stride) {
+    const IT first = xcd_order<IT, kXcdRunElem>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    for (IT g = first; g < n_items; g += stride) {
         const IT i = expand<IT>(g, fx);
         int j = 0;
 #pragma unroll
@@ -408,7 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_monomial(typename V2<R>::T *__restri
     using C2 = typename V2<R>::T;
     constexpr int D = 1 << K;
     const IT stride = IT(gridDim.x) * kBlock;
-    for (IT g = IT(blockIdx.x) * kBlock + threadIdx.x; g < n_groups; g += stride) {
+    const IT first = xcd_order<IT, kXcdRunElem>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    for (IT g = first; g < n_groups; g += stride) {
         C2 *p = psi + expand<IT>(g, fx);
         C2 v[D];
 #pragma unroll
