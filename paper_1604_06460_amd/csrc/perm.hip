@@ -182,7 +182,10 @@ __device__ __forceinline__ void div_source(uint32_t &a, uint32_t &c, uint32_t b,
 // bits are the rest of t in order: the whole device then works inside one or
 // two such slices at a time, which stay in cache while their scattered reads
 // are served. It pays for division when a sits above c: every input of a
-// clean-c output lies in another a row.
+// clean-c output lies in another a row. Multiplication walks the blocks in
+// chunked XCD order (runs of 128), which on 30 qubits with c lowest takes
+// 5.5 instead of 6.2 ms; the same order makes division slower (20 instead of
+// 15 ms), so division keeps the launch order.
 template <typename R, typename IT, int KIND>
 __global__ __launch_bounds__(kThreads) void k_arith_gather(
     const typename V2<R>::T *__restrict__ in, typename V2<R>::T *__restrict__ out, IT dim,
@@ -193,7 +196,8 @@ __global__ __launch_bounds__(kThreads) void k_arith_gather(
     const IT stride = IT(gridDim.x) * kThreads;
     const int nrest = n - aa.m;
     const IT below_b = (IT(1) << aa.b_lo) - 1;
-    for (IT t = IT(blockIdx.x) * kThreads + threadIdx.x; t < dim; t += stride) {
+    const IT first = KIND == QS_ARITH_MUL ? xcd_order<IT, 128>(blockIdx.x, gridDim.x) : IT(blockIdx.x);
+    for (IT t = first * kThreads + threadIdx.x; t < dim; t += stride) {
         IT i = t;
         if (bmajor) {
             const IT r = t & ((IT(1) << nrest) - 1);

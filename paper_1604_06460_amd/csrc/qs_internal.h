@@ -66,6 +66,23 @@ struct qs_state {
 namespace qs {
 
 // ---------------------------------------------------------------------------
+// Workgroup order over the 8 XCDs. The dispatcher hands workgroup b to XCD
+// b mod 8, so in launch order every XCD takes every eighth tile. xcd_order
+// gives XCD x runs of C consecutive tiles instead (tile = run * 8C + x * C +
+// offset): each XCD stays on nearby addresses (its own L2, fewer DRAM pages
+// open) while all eight stay in the same region of the buffer. Grids that
+// are not a multiple of 8C keep the launch order, so the map is always a
+// bijection on [0, G).
+// ---------------------------------------------------------------------------
+template <typename IT, unsigned C>
+__device__ __forceinline__ IT xcd_order(unsigned b, unsigned G)
+{
+    if (G % (8 * C)) return IT(b);
+    const unsigned i = b / 8;
+    return IT(i / C) * IT(8 * C) + IT(b % 8) * IT(C) + IT(i % C);
+}
+
+// ---------------------------------------------------------------------------
 // Gate descriptors passed to the sweep launchers (host side).
 // ---------------------------------------------------------------------------
 enum GateClass { GC_IDENTITY, GC_PHASE1, GC_DIAG, GC_MONOMIAL, GC_DENSE };

@@ -68,22 +68,11 @@ __device__ __forceinline__ void store_amp(C2 *p, C2 v, int nt)
     }
 }
 
-// Workgroup order over the 8 XCDs. The dispatcher hands workgroup b to XCD
-// b mod 8, so in launch order every XCD would take every eighth tile. Here
-// XCD x takes runs of C consecutive tiles (tile = run * 8C + x * C + offset),
-// which keeps each XCD on nearby addresses while all eight stay in the same
-// region of the state. Measured on 30-qubit complex128 sweeps: C = 64 for
-// the dense block sweeps and C = 128 for the elementwise gate kernels beat
-// both the launch order (6.37 -> 6.01 ms per 4-qubit block, 1015 -> 969 ms
-// for the gate-level QFT) and one contiguous eighth per XCD. Grids that are
-// not a multiple of 8C keep the launch order.
-template <typename IT, unsigned C>
-__device__ __forceinline__ IT xcd_order(unsigned b, unsigned G)
-{
-    if (G % (8 * C)) return IT(b);
-    const unsigned i = b / 8;
-    return IT(i / C) * IT(8 * C) + IT(b % 8) * IT(C) + IT(i % C);
-}
+// Chunked XCD workgroup order (xcd_order, qs_internal.h): C = 64 for the
+// dense block sweeps and C = 128 for the elementwise gate kernels beat both
+// the launch order (6.37 -> 6.01 ms per 4-qubit block, 1015 -> 969 ms for
+// the gate-level QFT on 30-qubit complex128 states) and one contiguous
+// eighth per XCD.
 constexpr unsigned kXcdRunDense = 64, kXcdRunElem = 128;
 
 template <typename IT>
