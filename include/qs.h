@@ -485,10 +485,12 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     2 wave tiles staged through LDS (needs n >= 6 + k; k <= 5 for
  *     complex128), 3 FP32 matrix cores (complex64, k = 6, n >= 12),
  *     4 workgroup tiles with the output rows split over the waves (k >= 5,
- *     n >= 6 + k). A path that does not apply to a block falls back to the
- *     default rule (matrix cores for complex64 k = 6, workgroup tiles for
- *     other blocks of 5 or 6 qubits, LDS below the line size, registers
- *     otherwise). Every path computes the same products; only the
+ *     n >= 6 + k), 5 workgroup-shared 1024-amplitude tiles with one load
+ *     per lane per tile row group (2 <= k <= 4, n >= 10). A path that does
+ *     not apply to a block falls back to the default rule (matrix cores for
+ *     complex64 k = 6, workgroup tiles for other blocks of 5 or 6 qubits,
+ *     shared 1024-amplitude tiles for complex128 blocks of 2 to 4 qubits on
+ *     20 or more qubits, LDS below the line size, registers otherwise). Every path computes the same products; only the
  *     summation order of the FP32/FP64 dot products may differ.
  *   QS_TUNE_SWEEP_WG_PER_CU (dtype, k, class, n bucket): cap of the dense
  *     sweep grid in workgroups per compute unit (grid-stride beyond it).

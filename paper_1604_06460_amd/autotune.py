@@ -101,7 +101,8 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
         mat = random_unitary(k, rng)
         for cls in (Q.QS_TCLS_SUBLINE, Q.QS_TCLS_SUBWAVE, Q.QS_TCLS_HIGH):
             sets = class_targets(cls, k, n, dtype)
-            paths = [1, 2] + ([3] if dtype == Q.QS_C64 and k == 6 else []) + ([4] if k >= 5 else [])
+            paths = [1, 2] + ([3] if dtype == Q.QS_C64 and k == 6 else []) + ([4] if k >= 5 else []) + \
+                ([5] if 2 <= k <= 4 else [])
             if dtype == Q.QS_C128 and k == 6:
                 paths = [1, 4]
 
@@ -109,19 +110,27 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
                 for t in sets:
                     st.apply_gate(t, mat)
 
+            # each path is timed with plain and with streaming loads and
+            # stores and keeps its better time: paths differ in how much the
+            # cache policy is worth to them
             times = {}
-            for p in paths:
+            for p in paths + [0]:
                 Q.tune_set(Q.QS_TUNE_SWEEP_PATH, p, dtype, k, cls, nb)
-                times[p] = timer.ms(run_sets, reps)
-            Q.tune_set(Q.QS_TUNE_SWEEP_PATH, 0, dtype, k, cls, nb)
-            times[0] = timer.ms(run_sets, reps)
+                tt = []
+                for ntv in (0, 3):
+                    Q.tune_set(Q.QS_TUNE_SWEEP_NT, ntv, dtype, k, cls, nb)
+                    tt.append(timer.ms(run_sets, reps))
+                times[p] = min(tt)
+            Q.tune_set(Q.QS_TUNE_SWEEP_NT, 0, dtype, k, cls, nb)
             path = _pick(times, 0, margin)
             Q.tune_set(Q.QS_TUNE_SWEEP_PATH, path, dtype, k, cls, nb)
             entries.append({"param": "sweep_path", "dtype": dtype, "k": k, "cls": cls, "nbucket": nb,
                             "value": int(path), "ms": {str(a): round(b, 4) for a, b in times.items()}})
-            # grid cap for the chosen path (the matrix-core path has its own)
+            # grid cap for the chosen path (the matrix-core path has its own,
+            # the shared-tile path launches one workgroup per tile)
+            tile_default = dtype == Q.QS_C128 and 2 <= k <= 4 and n >= 20
             gtimes = {}
-            if path in (1, 2, 4) or (path == 0 and k <= 4):
+            if path in (1, 2, 4) or (path == 0 and k <= 4 and not tile_default):
                 for g in (0, 8, 32, 128):
                     Q.tune_set(Q.QS_TUNE_SWEEP_WG_PER_CU, g, dtype, k, cls, nb)
                     gtimes[g] = timer.ms(run_sets, reps)
@@ -130,9 +139,9 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
                 entries.append({"param": "sweep_wg_per_cu", "dtype": dtype, "k": k, "cls": cls,
                                 "nbucket": nb, "value": int(g),
                                 "ms": {str(a): round(b, 4) for a, b in gtimes.items()}})
-            # cache policy of the register and LDS-staged paths
+            # cache policy of the register, LDS-staged and shared-tile paths
             ntimes = {}
-            if path in (1, 2) or (path == 0 and k <= 4):
+            if path in (1, 2, 5) or (path == 0 and k <= 4):
                 for ntv in (0, 1, 2, 3):
                     Q.tune_set(Q.QS_TUNE_SWEEP_NT, ntv, dtype, k, cls, nb)
                     ntimes[ntv] = timer.ms(run_sets, reps)

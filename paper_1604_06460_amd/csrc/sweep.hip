@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 namespace qs {
 namespace {
@@ -44,6 +45,19 @@ template <> struct V2<float> { using T = float2; };
 template <typename C2> struct NtVec;
 template <> struct NtVec<double2> { typedef double __attribute__((ext_vector_type(2))) T; };
 template <> struct NtVec<float2> { typedef float __attribute__((ext_vector_type(2))) T; };
+
+// Kernels take the policy as a template parameter: a runtime flag puts a
+// branch around every access and serialises the stores.
+template <typename F>
+void with_nt(int nt, F &&f)
+{
+    switch (nt & 3) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 3>{}); break;
+    }
+}
 
 template <typename C2>
 __device__ __forceinline__ C2 load_amp(const C2 *p, int nt)
@@ -129,10 +143,10 @@ __device__ __forceinline__ void row_dot(const R *__restrict__ row, const C2 (&v)
     }
 }
 
-template <typename R, int K, typename IT>
+template <typename R, int K, typename IT, int NT>
 __global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict__ psi,
                                                   const R *__restrict__ mat, IT n_groups,
-                                                  FixArgs fx, OffArgs<(1 << K)> off, int nt)
+                                                  FixArgs fx, OffArgs<(1 << K)> off)
 {
     using C2 = typename V2<R>::T;
     constexpr int D = 1 << K;
@@ -142,12 +156,12 @@ __global__ __launch_bounds__(kBlock) void k_dense(typename V2<R>::T *__restrict_
         C2 *p = psi + expand<IT>(g, fx);
         C2 v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = load_amp(p + off.o[j], nt);
+        for (int j = 0; j < D; ++j) v[j] = load_amp(p + off.o[j], NT);
 #pragma unroll 1
         for (int j = 0; j < D; ++j) {
             R re = R(0), im = R(0);
             row_dot<R, C2, D>(mat + 2 * j * D, v, re, im);
-            store_amp(p + off.o[j], C2{re, im}, nt);
+            store_amp(p + off.o[j], C2{re, im}, NT);
         }
     }
 }
@@ -176,11 +190,11 @@ __device__ __forceinline__ int lds_slot(int p)
     return p ^ ((p / SW) & (SW - 1));
 }
 
-template <typename R, int K, typename IT>
+template <typename R, int K, typename IT, int NT>
 __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict__ psi,
                                                   const R *__restrict__ mat, IT n_tiles,
                                                   FixArgs fx, OffArgs<(1 << K)> offl,
-                                                  LdsArgs<(1 << K)> la, int nt)
+                                                  LdsArgs<(1 << K)> la)
 {
     using C2 = typename V2<R>::T;
     constexpr int D = 1 << K;
@@ -193,7 +207,7 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict_
         C2 *p = psi + expand<IT>(t, fx) + lane;
         C2 v[D];
 #pragma unroll
-        for (int r = 0; r < D; ++r) v[r] = load_amp(p + offl.o[r], nt);
+        for (int r = 0; r < D; ++r) v[r] = load_amp(p + offl.o[r], NT);
 #pragma unroll
         for (int r = 0; r < D; ++r) tile[lds_slot<C2>(lane + 64 * r)] = v[r];
         __syncthreads();
@@ -207,9 +221,87 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::T *__restrict_
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < D; ++r) store_amp(p + offl.o[r], tile[lds_slot<C2>(lane + 64 * r)], nt);
+        for (int r = 0; r < D; ++r) store_amp(p + offl.o[r], tile[lds_slot<C2>(lane + 64 * r)], NT);
         __syncthreads();
     }
+}
+
+// Dense sweep for blocks of 2 to 4 qubits with the tile shared by a
+// workgroup of 256 threads. A tile is 1024 amplitudes: the 2^K values of the
+// targets times the 2^(10-K) values of the lowest free bits (the columns).
+// Tile entry e lives at the address that deposits e's ten bits into the ten
+// tile bits (ascending), and thread tid loads entries tid + 256u, u = 0..3:
+// bits 0-5 are always tile bits, so each wave reads 1 KiB of consecutive
+// amplitudes per load, and each lane has four loads in flight where a lane
+// that owns a whole group has 2^K. After a barrier, thread tid computes
+// four output rows of one column from LDS; the rows are uniform across the
+// wave, so the matrix entries are scalar operands. The outputs go to a
+// second LDS tile and leave with the load pattern. One tile per workgroup
+// (the grid is the tile count): with a tile loop the compiler hoists the
+// four matrix rows out of it and spills scalar registers.
+template <int K>
+struct TileArgs {
+    int tb[10];          // absolute tile bit positions, ascending
+    int cpos[10 - K];    // tile-index position of each column bit, ascending
+    int offc[1 << K];    // tile-index offset of local index j (bit m <-> target m)
+};
+
+template <typename R, int K, typename IT, int NT>
+__global__ __launch_bounds__(256) void k_dense_tile(typename V2<R>::T *__restrict__ psi,
+                                                    const R *__restrict__ mat, IT n_tiles,
+                                                    FixArgs ft, TileArgs<K> ta)
+{
+    using C2 = typename V2<R>::T;
+    constexpr int D = 1 << K, NG = D / 4, WPG = 4 / NG;   // row groups, waves per row group
+    static_assert(K >= 2 && K <= 4, "four output rows per thread, 1024-entry tile");
+    __shared__ C2 tin[1024];
+    __shared__ C2 tout[1024];
+    const int tid = int(threadIdx.x);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = wave / WPG;                          // output rows 4g .. 4g + 3
+    const int col = (wave % WPG) * 64 + (tid & 63);
+    int ct = 0;
+#pragma unroll
+    for (int i = 0; i < 10 - K; ++i) ct |= ((col >> i) & 1) << ta.cpos[i];
+    IT off[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u;
+        IT o = 0;
+#pragma unroll
+        for (int i = 0; i < 10; ++i) o |= IT((e >> i) & 1) << ta.tb[i];
+        off[u] = o;
+    }
+    const R *rows = mat + 2 * (4 * g) * D;
+    const IT t = xcd_order<IT, kXcdRunDense>(blockIdx.x, gridDim.x);
+    if (t >= n_tiles) return;   // whole workgroup: the barriers below stay uniform
+    C2 *p = psi + expand<IT>(t, ft);
+    C2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = load_amp(p + off[u], NT);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tin[lds_slot<C2>(tid + 256 * u)] = v[u];
+    __syncthreads();
+    R re[4] = {R(0), R(0), R(0), R(0)}, im[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        const C2 x = tin[lds_slot<C2>(ct | ta.offc[c])];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const R mr = rows[2 * (q * D + c)], mi = rows[2 * (q * D + c) + 1];
+            re[q] = fma(mr, x.x, re[q]);
+            re[q] = fma(-mi, x.y, re[q]);
+            im[q] = fma(mr, x.y, im[q]);
+            im[q] = fma(mi, x.x, im[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tout[lds_slot<C2>(ct | ta.offc[4 * g + q])] = C2{re[q], im[q]};
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = tout[lds_slot<C2>(tid + 256 * u)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) store_amp(p + off[u], v[u], NT);
 }
 
 // Dense sweep for wide blocks (K = 5, 6) whose groups do not fit one
@@ -529,6 +621,41 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
     if constexpr (sizeof(R) == 4 && K == 6) {
         if ((path == 0 || path == 3) && mfma_applicable(h, d)) return launch_dense_mfma(h, d, dmat);
     }
+    // complex128 blocks of 2 to 4 qubits on states of 20 qubits or more
+    // default to the workgroup-shared 1024-amplitude tile
+    if constexpr (K >= 2 && K <= 4) {
+        const bool wt_ok = d.ctrl_mask == 0 && h->n >= 10;
+        if (wt_ok && (path == 5 || (path == 0 && sizeof(R) == 8 && h->n >= 20))) {
+            uint64_t tmask = 0;
+            for (int i = 0; i < K; ++i) tmask |= 1ull << d.targets[i];
+            std::vector<int> tb(d.targets, d.targets + K), cols;
+            for (int b = 0; int(cols.size()) < 10 - K; ++b)
+                if (!((tmask >> b) & 1)) cols.push_back(b);
+            tb.insert(tb.end(), cols.begin(), cols.end());
+            std::sort(tb.begin(), tb.end());
+            auto tpos = [&](int b) { return int(std::lower_bound(tb.begin(), tb.end(), b) - tb.begin()); };
+            TileArgs<K> ta;
+            for (int i = 0; i < 10; ++i) ta.tb[i] = tb[size_t(i)];
+            for (int i = 0; i < 10 - K; ++i) ta.cpos[i] = tpos(cols[size_t(i)]);
+            for (int j = 0; j < D; ++j) {
+                int o = 0;
+                for (int m = 0; m < K; ++m)
+                    if ((j >> m) & 1) o |= 1 << tpos(d.targets[m]);
+                ta.offc[j] = o;
+            }
+            FixArgs ft;
+            if (int rc = make_fix(tb.data(), 10, 0, ft)) return rc;
+            const IT n_tiles = IT(h->dim() >> 10);
+            if (uint64_t(n_tiles) > 0x7fffffffull) return fail(QS_EUNSUPPORTED, "tile grid of %llu workgroups", (unsigned long long)n_tiles);
+            const unsigned grid = unsigned(n_tiles);   // one tile per workgroup; no grid cap
+            with_nt(nt, [&](auto c) {
+                hipLaunchKernelGGL((k_dense_tile<R, K, IT, decltype(c)::value>), dim3(grid), dim3(256), 0,
+                                   h->stream, psi, m, n_tiles, ft, ta);
+            });
+            QS_HIP(hipGetLastError());
+            return QS_OK;
+        }
+    }
     // by default, targets inside a 128-byte line stage the tile through LDS
     // (one wave per tile); wide complex128 blocks share a tile per workgroup
     constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
@@ -581,8 +708,10 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
                     hipLaunchKernelGGL((k_dense_wide<R, K, IT>), dim3(grid), dim3(256), 0, h->stream, psi, m,
                                        n_tiles, ft, offl, la);
             } else if constexpr (lds_capable) {
-                hipLaunchKernelGGL((k_dense_lds<R, K, IT>), dim3(grid), dim3(64), 0, h->stream, psi,
-                                   m, n_tiles, ft, offl, la, nt);
+                with_nt(nt, [&](auto c) {
+                    hipLaunchKernelGGL((k_dense_lds<R, K, IT, decltype(c)::value>), dim3(grid), dim3(64), 0,
+                                       h->stream, psi, m, n_tiles, ft, offl, la);
+                });
             }
             QS_HIP(hipGetLastError());
             return QS_OK;
@@ -593,8 +722,10 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
         hipLaunchKernelGGL((k_dense_split<R, K, 8, IT>), dim3(capped(grid_for(uint64_t(n_groups) * (D / 8)))),
                            dim3(kBlock), 0, h->stream, psi, m, n_groups, fx, off);
     } else {
-        hipLaunchKernelGGL((k_dense<R, K, IT>), dim3(capped(grid_for(n_groups))), dim3(kBlock), 0,
-                           h->stream, psi, m, n_groups, fx, off, nt);
+        with_nt(nt, [&](auto c) {
+            hipLaunchKernelGGL((k_dense<R, K, IT, decltype(c)::value>), dim3(capped(grid_for(n_groups))),
+                               dim3(kBlock), 0, h->stream, psi, m, n_groups, fx, off);
+        });
     }
     QS_HIP(hipGetLastError());
     return QS_OK;

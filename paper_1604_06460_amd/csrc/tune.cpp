@@ -25,7 +25,7 @@ struct Range {
 Range range_of(int p)
 {
     switch (p) {
-    case QS_TUNE_SWEEP_PATH: return {1, 4};
+    case QS_TUNE_SWEEP_PATH: return {1, 5};
     case QS_TUNE_SWEEP_WG_PER_CU: return {1, 4096};
     case QS_TUNE_FFT_DIGIT: return {2, 10};
     case QS_TUNE_FFT_LDS_KB: return {8, 160};

@@ -139,7 +139,7 @@ def test_tune_table_set_get_and_wildcards(clean_tune):
     (0, -1, 9, -1, -1, 1),                     # k
     (0, -1, -1, 3, -1, 1),                     # class
     (0, -1, -1, -1, 3, 1),                     # n bucket
-    (0, -1, -1, -1, -1, 5),                    # path value
+    (0, -1, -1, -1, -1, 6),                    # path value
     (2, -1, -1, -1, -1, 11),                   # FFT digit
     (3, -1, -1, -1, -1, 200),                  # FFT LDS KiB
     (4, -1, -1, -1, -1, 17),                   # MFMA WG/CU

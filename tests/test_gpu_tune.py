@@ -47,7 +47,7 @@ def test_every_sweep_path_matches_oracle(Q, O, S, dtype, k):
         assert Q.tune_classify(dtype, n, t)[0] == cls
         m = _unitary(k, rng)
         ref = O.apply_gate(psi0.copy(), t, m)
-        for path in (1, 2, 3, 4):
+        for path in (1, 2, 3, 4, 5):
             for cap, nt in ((0, 0), (1, 3)):   # cap 1: one workgroup per CU, grid-stride; nt 3: streaming
                 Q.tune_set(Q.QS_TUNE_SWEEP_PATH, path, dtype, k, cls, -1)
                 Q.tune_set(Q.QS_TUNE_SWEEP_WG_PER_CU, cap, dtype, k, cls, -1)
@@ -58,6 +58,35 @@ def test_every_sweep_path_matches_oracle(Q, O, S, dtype, k):
                 got = st.get().astype(np.complex128)
                 st.free()
                 assert np.abs(got - ref).max() < TOL[dtype], (dtype, k, cls, path, cap, nt)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_shared_tile_sweep_matches_oracle(Q, O, S, dtype, k):
+    """The workgroup-shared 1024-amplitude tile (path 5, the complex128
+    default for 2 to 4 qubits on 20 or more qubits) at 22 qubits, where its
+    4096 workgroups take the chunked XCD order, and at 19 (512 tiles).
+    Targets inside a cache line, inside a wave, above it and at or above
+    qubit 20, given in arbitrary order, with both cache policies."""
+    rng = np.random.default_rng(300 + 10 * k + dtype)
+    sets = {22: [[3, 0, 21, 9], [0, 1, 2, 3], [5, 6, 7, 8], [21, 20, 19, 12], [4, 13, 2, 17]],
+            19: [[18, 0, 7, 2], [6, 9, 13, 17]]}
+    for n, ts in sets.items():
+        psi0 = S.normal_state(n, 40 + n + k)
+        for t in ts:
+            t = t[:k]
+            m = _unitary(k, rng)
+            ref = O.apply_gate(psi0.copy(), t, m)
+            for nt in (0, 3):
+                cls = Q.tune_classify(dtype, n, t)[0]
+                Q.tune_set(Q.QS_TUNE_SWEEP_PATH, 5, dtype, k, cls, -1)
+                Q.tune_set(Q.QS_TUNE_SWEEP_NT, nt, dtype, k, cls, -1)
+                st = Q.State(n, dtype)
+                st.set(psi0)
+                st.apply_gate(t, m)
+                got = st.get().astype(np.complex128)
+                st.free()
+                assert np.abs(got - ref).max() < TOL[dtype], (dtype, k, n, t, nt)
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
