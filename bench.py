@@ -436,8 +436,9 @@ def main():
     achieved = 2 * amp * N / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "fused block sweeps, blocks of up to 4 qubits (k_dense_lds / k_dense per the tuned "
-                          "table, k_diag for diagonal blocks), average over the step's launches",
+                "kernel": "fused block sweeps, blocks of up to 4 qubits (k_dense_tile, the tuned default for "
+                          "complex128 blocks of 2 to 4 qubits, and k_diag for diagonal blocks), average over "
+                          "the step's launches",
                 "avg_launch_ms": round(sweep_ms, 4), "bytes_per_launch": 2 * amp * N}
 
     # at-scale consistency (untimed): gate-level QFT then emulated inverse
