@@ -493,7 +493,8 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     20 or more qubits, LDS below the line size, registers otherwise). Every path computes the same products; only the
  *     summation order of the FP32/FP64 dot products may differ.
  *   QS_TUNE_SWEEP_WG_PER_CU (dtype, k, class, n bucket): cap of the dense
- *     sweep grid in workgroups per compute unit (grid-stride beyond it).
+ *     sweep grid in workgroups per compute unit (grid-stride beyond it);
+ *     path 5 ignores it (one workgroup per tile).
  *   QS_TUNE_FFT_DIGIT (dtype, -, -, n bucket): largest FFT digit (bits per
  *     pass), 2..10.
  *   QS_TUNE_FFT_LDS_KB (dtype, -, -, n bucket): LDS tile budget of an FFT

@@ -366,11 +366,13 @@ def test_load_device_streaming_copy_and_fallbacks(Q, S, dtype):
     """qs_load_device copies with the library's 16-byte streaming kernel when
     both buffers are 16-byte aligned and falls back to the runtime copy
     otherwise (a complex64 source one amplitude, 8 bytes, into a tensor):
-    both paths move the amplitudes bit for bit, from 2 to 2^17 amplitudes;
-    an overlapping source is rejected."""
+    both paths move the amplitudes bit for bit, from 2 to 2^21 amplitudes
+    (at 2^21 the copy's 1024-thread blocks number 2048 (complex128) or 1024
+    (complex64), enough for the chunked XCD order); an overlapping source is
+    rejected."""
     import torch
     tdt = torch.complex128 if dtype == 1 else torch.complex64
-    for n in (1, 2, 7, 17):
+    for n in (1, 2, 7, 17, 21):
         x = torch.randn((1 << n) + 1, dtype=tdt, device="cuda")
         ref = x.cpu().numpy()
         for off in (0, 1):                                 # aligned, then one amplitude in
