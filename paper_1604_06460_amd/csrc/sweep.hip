@@ -41,7 +41,10 @@ template <> struct V2<double> { using T = double2; };
 template <> struct V2<float> { using T = float2; };
 
 // Nontemporal (streaming) loads and stores of one amplitude, selected by a
-// tuning flag: bit 0 stores, bit 1 loads.
+// tuning flag: bit 0 stores, bit 1 loads. The elementwise gate kernels
+// (phases, diagonals, monomials) always stream: on 30-qubit complex128
+// states a controlled phase takes 1.26-1.36 ms that way and 1.43 ms with
+// plain accesses.
 template <typename C2> struct NtVec;
 template <> struct NtVec<double2> { typedef double __attribute__((ext_vector_type(2))) T; };
 template <> struct NtVec<float2> { typedef float __attribute__((ext_vector_type(2))) T; };
@@ -438,8 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_phase1(typename V2<R>::T *__restrict
     const IT first = xcd_order<IT, kXcdRunElem>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     for (IT g = first; g < n_items; g += stride) {
         C2 *p = psi + expand<IT>(g, fx);
-        const C2 a = *p;
-        *p = C2{pr * a.x - pi * a.y, pr * a.y + pi * a.x};
+        const C2 a = load_amp(p, 3);
+        store_amp(p, C2{pr * a.x - pi * a.y, pr * a.y + pi * a.x}, 3);
     }
 }
 
@@ -459,9 +462,9 @@ __global__ __launch_bounds__(kBlock) void k_phase1_lines(typename V2<R>::T *__re
     const IT first = xcd_order<IT, kXcdRunElem>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     for (IT g = first; g < n_items; g += stride) {
         C2 *p = psi + expand<IT>(g, fx);
-        C2 a = *p;
+        C2 a = load_amp(p, 3);
         if ((uint64_t(p - psi) & low_mask) == low_vals) a = C2{pr * a.x - pi * a.y, pr * a.y + pi * a.x};
-        *p = a;
+        store_amp(p, a, 3);
     }
 }
 
@@ -487,8 +490,8 @@ __global__ __launch_bounds__(kBlock) void k_diag(typename V2<R>::T *__restrict__
 #pragma unroll
         for (int m = 0; m < K; ++m) j |= int((i >> tg.o[m]) & 1) << m;
         const R dr = dsh[2 * j], di = dsh[2 * j + 1];
-        const C2 a = psi[i];
-        psi[i] = C2{dr * a.x - di * a.y, dr * a.y + di * a.x};
+        const C2 a = load_amp(psi + i, 3);
+        store_amp(psi + i, C2{dr * a.x - di * a.y, dr * a.y + di * a.x}, 3);
     }
 }
 
@@ -517,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_monomial(typename V2<R>::T *__restri
         C2 v[D];
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            if ((ma.touched >> j) & 1) v[j] = p[off.o[j]];
+            if ((ma.touched >> j) & 1) v[j] = load_amp(p + off.o[j], 3);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             if (!((ma.touched >> j) & 1)) continue;
@@ -526,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_monomial(typename V2<R>::T *__restri
                 const R cr = ma.coef[2 * j], ci = ma.coef[2 * j + 1];
                 x = C2{cr * v[j].x - ci * v[j].y, cr * v[j].y + ci * v[j].x};
             }
-            p[off.o[ma.dst[j]]] = x;
+            store_amp(p + off.o[ma.dst[j]], x, 3);
         }
     }
 }
