@@ -67,10 +67,13 @@ def test_shared_tile_sweep_matches_oracle(Q, O, S, dtype, k):
     default for 2 to 4 qubits on 20 or more qubits) at 22 qubits, where its
     4096 workgroups take the chunked XCD order, and at 19 (512 tiles).
     Targets inside a cache line, inside a wave, above it and at or above
-    qubit 20, given in arbitrary order, with both cache policies."""
+    qubit 20, given in arbitrary order, with both cache policies. At 10
+    qubits, the smallest state the path takes, the tile is the whole state
+    and the grid one workgroup."""
     rng = np.random.default_rng(300 + 10 * k + dtype)
     sets = {22: [[3, 0, 21, 9], [0, 1, 2, 3], [5, 6, 7, 8], [21, 20, 19, 12], [4, 13, 2, 17]],
-            19: [[18, 0, 7, 2], [6, 9, 13, 17]]}
+            19: [[18, 0, 7, 2], [6, 9, 13, 17]],
+            10: [[9, 0, 5, 3], [6, 7, 8, 9]]}
     for n, ts in sets.items():
         psi0 = S.normal_state(n, 40 + n + k)
         for t in ts:
