@@ -6,9 +6,10 @@ Times candidate launch parameters on the current device and writes the JSON
 table that the binding applies at import (qs.TUNED_FILE):
 
   * dense sweep path (registers / LDS-staged wave tiles / matrix cores /
-    workgroup tiles with rows split over waves), its cache policy and
-    the grid cap in workgroups per CU, per (dtype, k, class of the lowest
-    target, n bucket);
+    workgroup tiles with rows split over waves / shared 1024-amplitude
+    tiles), its cache policy and the grid cap in workgroups per CU, per
+    (dtype, k, class of the lowest target, n bucket); each path is timed
+    with plain and with streaming accesses and keeps its better time;
   * FFT digit width and LDS tile budget per (dtype, n bucket);
   * persistent grid of the matrix-core sweep (complex64, k = 6);
   * batch gang sizing and barrier cost.
