@@ -41,10 +41,11 @@ template <> struct V2<double> { using T = double2; };
 template <> struct V2<float> { using T = float2; };
 
 // Nontemporal (streaming) loads and stores of one amplitude, selected by a
-// tuning flag: bit 0 stores, bit 1 loads. The elementwise gate kernels
-// (phases, diagonals, monomials) always stream: on 30-qubit complex128
-// states a controlled phase takes 1.26-1.36 ms that way and 1.43 ms with
-// plain accesses.
+// tuning flag: bit 0 stores, bit 1 loads. The phase and diagonal kernels
+// always stream: on 30-qubit complex128 states a controlled phase takes
+// 1.26-1.36 ms that way and 1.43 ms with plain accesses. Monomial gates
+// keep plain accesses: they write partial lines, which streaming stores
+// made 10% slower (controlled X gates of a 31-qubit adder network).
 template <typename C2> struct NtVec;
 template <> struct NtVec<double2> { typedef double __attribute__((ext_vector_type(2))) T; };
 template <> struct NtVec<float2> { typedef float __attribute__((ext_vector_type(2))) T; };
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_monomial(typename V2<R>::T *__restri
         C2 v[D];
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            if ((ma.touched >> j) & 1) v[j] = load_amp(p + off.o[j], 3);
+            if ((ma.touched >> j) & 1) v[j] = p[off.o[j]];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             if (!((ma.touched >> j) & 1)) continue;
@@ -529,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_monomial(typename V2<R>::T *__restri
                 const R cr = ma.coef[2 * j], ci = ma.coef[2 * j + 1];
                 x = C2{cr * v[j].x - ci * v[j].y, cr * v[j].y + ci * v[j].x};
             }
-            store_amp(p + off.o[ma.dst[j]], x, 3);
+            p[off.o[ma.dst[j]]] = x;
         }
     }
 }
