@@ -239,15 +239,51 @@ def test_gate_level_modmul_bit_exact(O, S, w, c, seed):
     assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
 
 
-def test_table_perm(O, S):
-    n, lo, nb = 7, 2, 3
-    dest = np.random.default_rng(0).permutation(1 << nb).astype(np.uint64)
-    psi = S.normal_state(n, 1)
-    got = O.table_perm(psi, lo, nb, dest)
-    for i in range(1 << n):
-        f = (i >> lo) & 7
-        j = (i & ~(7 << lo)) | (int(dest[f]) << lo)
-        assert got[j] == psi[i]
+def test_table_perm_bit_reversal_equals_swap_network(O, S):
+    """A field permutation given as a table (Sec. III-A: any classical
+    bijection on basis states) must equal the same map built from gates. The
+    bit reversal of an m-bit field is the SWAP network (q, m-1-q) run by the
+    gate simulator; both are moves, so they agree bit for bit."""
+    for (n, lo, nb, seed) in [(7, 2, 3, 1), (8, 0, 8, 2), (9, 3, 5, 3), (6, 1, 4, 4)]:
+        dest = np.array([int(format(f, "0%db" % nb)[::-1], 2) for f in range(1 << nb)],
+                        dtype=np.uint64)
+        psi = S.normal_state(n, seed)
+        got = O.table_perm(psi, lo, nb, dest)
+        gates = [S.swap(lo + q, lo + nb - 1 - q) for q in range(nb // 2)]
+        ref = O.apply_circuit(psi, gates)
+        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+def test_table_perm_increment_equals_cnot_ladder(O, S):
+    """x -> x + 1 mod 2^m on a field, as a table, against the textbook
+    multi-controlled-X incrementer (flip bit j when all lower bits are 1,
+    highest bit first)."""
+    for (n, lo, nb, seed) in [(7, 2, 4, 5), (6, 0, 6, 6)]:
+        dest = np.array([(f + 1) % (1 << nb) for f in range(1 << nb)], dtype=np.uint64)
+        psi = S.normal_state(n, seed)
+        got = O.table_perm(psi, lo, nb, dest)
+        gates = [S.mcx([lo + q for q in range(j)], lo + j) for j in range(nb - 1, -1, -1)]
+        ref = O.apply_circuit(psi, gates)
+        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+def test_table_perm_modmul_table_equals_modmul(O, S):
+    """The controlled modular multiplication written as a table over the
+    joint (work, control) field, with a^c mod N from Python's pow, must place
+    every amplitude where the modmul oracle does (itself pinned against the
+    Cuccaro network), bit for bit."""
+    for (w, c, lo, n, seed) in [(5, 2, 1, 9, 7), (4, 3, 0, 8, 8), (6, 0, 2, 9, 9)]:
+        a, N = S.modmul_params(w, seed)
+        nb = w + c
+        dest = np.zeros(1 << nb, dtype=np.uint64)
+        for f in range(1 << nb):
+            cc, x = f >> w, f & ((1 << w) - 1)
+            xp = (pow(a, cc, N) * x) % N if x < N else x
+            dest[f] = (cc << w) | xp
+        psi = S.normal_state(n, seed)
+        got = O.table_perm(psi, lo, nb, dest)
+        ref = O.modmul(psi, lo, w, lo + w, c, a, N)
+        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
 
 
 # ---------------------------------------------------------------------------
@@ -398,6 +434,44 @@ def test_adam_first_step_is_signed_lr():
     v = [np.zeros(3)]
     MLP.adam(p, g, m, v, 1, lr=0.01)
     assert np.abs(p[0] - (np.array([1.0, -2.0, 3.0]) - 0.01 * np.sign(g[0]))).max() < 1e-7
+
+
+def test_adam_constant_gradient_closed_form():
+    """With the same gradient g at every step, bias correction makes the
+    corrected moments exactly g and g^2 at every t, so step t moves each
+    parameter by lr*g/(|g|+eps): after t steps p = p0 - t*lr*g/(|g|+eps).
+    A wrong bias-correction exponent fails from t = 2 on."""
+    from oracle.oracle import MLP
+    p0 = np.array([0.3, -1.0, 2.0, 0.0])
+    g = np.array([0.25, -3.0, 1e-4, 7.0])
+    p, m, v = [p0.copy()], [np.zeros(4)], [np.zeros(4)]
+    lr, eps = 0.01, 1e-8
+    for t in range(1, 6):
+        MLP.adam(p, [g], m, v, t, lr=lr, eps=eps)
+        assert np.abs(p[0] - (p0 - t * lr * g / (np.abs(g) + eps))).max() < 1e-13
+        assert np.abs(m[0] - (1 - 0.9 ** t) * g).max() < 1e-14
+        assert np.abs(v[0] - (1 - 0.999 ** t) * g * g).max() < 1e-12
+
+
+def test_adam_alternating_gradient_closed_form():
+    """Gradients g_s = (-1)^s g: the first moment is a geometric series,
+    m_t = (1-b1) g (-1)^t (1-(-b1)^t)/(1+b1), while v_t = (1-b2^t) g^2 as for a
+    constant gradient. Step t then moves p by -lr*mh/(sqrt(vh)+eps) with
+    mh = m_t/(1-b1^t), vh = g^2."""
+    from oracle.oracle import MLP
+    b1, b2, lr, eps = 0.9, 0.999, 0.02, 1e-8
+    p0 = np.array([1.0, -0.5, 0.25])
+    g = np.array([0.5, -2.0, 3.0])
+    p, m, v = [p0.copy()], [np.zeros(3)], [np.zeros(3)]
+    want = p0.copy()
+    for t in range(1, 6):
+        gt = ((-1) ** t) * g
+        MLP.adam(p, [gt], m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        mt = (1 - b1) * g * ((-1) ** t) * (1 - (-b1) ** t) / (1 + b1)
+        mh = mt / (1 - b1 ** t)
+        want = want - lr * mh / (np.abs(g) + eps)
+        assert np.abs(m[0] - mt).max() < 1e-14
+        assert np.abs(p[0] - want).max() < 1e-12
 
 
 # ---------------------------------------------------------------------------
