@@ -72,7 +72,7 @@ def test_every_target_position_k1(Q, O, S, dtype):
             U = _rand_unitary(rng, 1)
             st.apply_gate([t], U)
             psi = O.apply_gate(psi, [t], U)
-        assert _err(st.get(), psi) < TOL[dtype] * 4
+        assert _err(st.get(), psi) < TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [1, 0])

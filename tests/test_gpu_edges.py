@@ -8,6 +8,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 2e-6, 1: 1e-13}
+TOL_FFT = {0: 1e-5, 1: 1e-12}   # the parity bars hold for the FFT passes too
 
 
 @pytest.fixture(scope="module")
@@ -67,9 +68,9 @@ def test_top_qubit_qft_and_full_register_qft(Q, O, S, dtype):
         st.set(psi)
         st.emulate_qft(q_lo, m)
         ref = O.qft_direct(psi, q_lo, m)
-        assert np.abs(st.get() - ref).max() < 10 * TOL[dtype], (q_lo, m)
+        assert np.abs(st.get() - ref).max() < TOL_FFT[dtype], (q_lo, m)
         st.emulate_qft(q_lo, m, inverse=True)
-        assert np.abs(st.get() - psi).max() < 10 * TOL[dtype], (q_lo, m)
+        assert np.abs(st.get() - psi).max() < TOL_FFT[dtype], (q_lo, m)
         st.free()
 
 

@@ -69,6 +69,7 @@ def test_32q_k6_complex64_norm_and_roundtrip(Q, S):
     inv = st.compile(S.inverse_circuit(gates), 6)
     st.run(inv)
     a0 = st.amplitudes([0, 1, (1 << n) - 1, 12345678])
-    assert abs(a0[0] - 1.0) < 1e-4
-    assert np.abs(a0[1:]).max() < 1e-4
+    print("32-qubit round trip: |a0 - 1| = %.3e, max other = %.3e" % (abs(a0[0] - 1.0), np.abs(a0[1:]).max()))
+    assert abs(a0[0] - 1.0) < 1e-5
+    assert np.abs(a0[1:]).max() < 1e-5
     st.free()

@@ -33,7 +33,7 @@ def _targets(cls, k, n, dtype, Q):
     return sorted([lo] + [n - 1 - 2 * i for i in range(k - 1)])
 
 
-TOL = {0: 2e-5, 1: 1e-12}   # complex64 / complex128, max abs error on a normalised state
+TOL = {0: 1e-5, 1: 1e-12}   # complex64 / complex128, max abs error on a normalised state
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
@@ -108,7 +108,7 @@ def test_every_fft_shape_matches_oracle(Q, O, S, dtype):
                 st.emulate_qft(q_lo, m)
                 got = st.get().astype(np.complex128)
                 st.free()
-                assert np.abs(got - ref).max() < 10 * TOL[dtype], (dtype, q_lo, m, digit, kb)
+                assert np.abs(got - ref).max() < TOL[dtype], (dtype, q_lo, m, digit, kb)
 
 
 def test_mfma_grid_sizes_match_oracle(Q, O, S):
