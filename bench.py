@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 N_QUBITS = 30
 DEPTH = 30
 MAX_K = 4
@@ -67,25 +68,209 @@ def measured_traffic():
     return d["traffic_bytes_per_launch"] if h == d.get("sweep_hip_sha256_prefix") else None
 
 
-def cpu_baseline(n, gates, budget_s=12.0):
+def host_info():
+    """CPU model and RAM of the host the oracle runs on."""
+    model, ram = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) * 1024 / 2 ** 30, 1)
+                break
+    except OSError:
+        pass
+    return model, ram
+
+
+def cpu_baseline(n, gates, budget_s=12.0, budget_1t_s=10.0):
     """The CPU oracle (plain gate-by-gate FP64 simulator) applying the first
-    gates of the same circuit to |0...0>; stops after ~budget_s seconds."""
+    gates of the same circuit to |0...0>; stops after ~budget_s seconds.
+    Run once with every host thread OpenMP gives it and once with one."""
     from oracle import oracle as O
-    psi = np.zeros(1 << n, dtype=np.complex128)
-    psi[0] = 1.0
-    done = 0
-    t0 = time.perf_counter()
-    while done < len(gates) and (done < 2 or time.perf_counter() - t0 < budget_s):
-        g = gates[done]
-        O.apply_gate(psi, g.targets, g.matrix, g.ctrl_mask, g.ctrl_vals)
-        done += 1
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    gbs = done * 2 * 16 * float(1 << n) / dt / 1e9
-    del psi
+
+    def run(budget):
+        psi = np.zeros(1 << n, dtype=np.complex128)
+        psi[0] = 1.0
+        done = 0
+        t0 = time.perf_counter()
+        while done < len(gates) and (done < 2 or time.perf_counter() - t0 < budget):
+            g = gates[done]
+            O.apply_gate(psi, g.targets, g.matrix, g.ctrl_mask, g.ctrl_vals)
+            done += 1
+        dt = time.perf_counter() - t0
+        del psi
+        return done, dt, done * 2 * 16 * float(1 << n) / dt / 1e9
+
+    cores = O.set_threads(0)
+    done, dt, gbs = run(budget_s)
+    O.set_threads(1)
+    done1, dt1, gbs1 = run(budget_1t_s)
+    O.set_threads(cores)
+    model, ram = host_info()
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
             "sample": "first %d gates (unfused, one sweep each) of the depth-%d %d-qubit circuit "
-                      "from |0...0>, complex128, %.1f s" % (done, DEPTH, n, dt)}
+                      "from |0...0>, complex128, %.1f s on %d threads" % (done, DEPTH, n, dt, cores),
+            "single_thread": {"value": round(gbs1, 3), "unit": "GB/s", "cores": 1,
+                              "sample": "first %d gates of the same circuit, %.1f s" % (done1, dt1)},
+            "cpu_model": model, "ram_gib": ram, "host_logical_cpus": os.cpu_count()}
+
+
+def config0_gate_level(Q, S):
+    """16 qubits, complex128, |0...0>, depth-20 random circuit applied gate
+    by gate (480 gates), then <Z_0>: wall time per circuit, host launches
+    included (synchronised before and after). The same circuit fused into
+    blocks of up to 4 qubits is timed too. The final state and <Z_0> are
+    compared with the oracle."""
+    from oracle import oracle as O
+    n, depth = 16, 20
+    gates = S.random_layer_circuit(n, depth, seed=S.SEED_BASE)
+    st = Q.State(n, Q.QS_C128)
+
+    def gate_level():
+        st.set_zero()
+        st.apply_gates(gates)
+        return st.expectation(z_mask=1).real
+
+    def fused():
+        st.set_zero()
+        prog = st.compile(gates, 4)
+        st.run(prog)
+        z = st.expectation(z_mask=1).real
+        prog.free()
+        return z
+
+    out = {"n_qubits": n, "depth": depth, "gates": len(gates), "dtype": "c128"}
+    for name, fn in (("gate_level", gate_level), ("fused_k4", fused)):
+        fn()
+        st.sync()
+        ts = []
+        for _ in range(20):
+            t0 = time.perf_counter()
+            z = fn()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        out[name + "_ms_per_circuit"] = round(float(np.median(ts)), 4)
+        out[name + "_z0"] = z
+    ref = O.apply_circuit(S.zero_state(n), gates)
+    gate_level()
+    out["max_abs_err_vs_oracle"] = float(np.abs(st.get() - ref).max())
+    out["z0_oracle"] = float(O.expectation(ref, z_mask=1).real)
+    st.free()
+    log("c0 16q gate-level: %.3f ms per circuit, fused %.3f ms"
+        % (out["gate_level_ms_per_circuit"], out["fused_k4_ms_per_circuit"]))
+    return out
+
+
+def config2_modmul28(Q, S):
+    """28-qubit complex128 state: 20-bit work register (qubits 0..19) in a
+    seeded normal state with distinct amplitudes, 8-bit control register
+    (qubits 20..27) in uniform superposition; |c>|x> -> |c>|a^c x mod N>
+    emulated as an index permutation. Timed with HIP events on the state's
+    stream; 4096 sampled outputs are checked bit for bit against the
+    oracle's per-index source map."""
+    import torch
+    from oracle import oracle as O
+    n, w, c = 28, 20, 8
+    a, N = S.modmul_params(w, S.SEED_BASE + 2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(S.SEED_BASE + 2)
+        v = torch.randn(1 << w, dtype=torch.complex128, device="cuda", generator=gen)
+        v /= torch.linalg.vector_norm(v) * (2.0 ** (c / 2))
+        x = v.repeat(1 << c)
+    stream.synchronize()
+    st = Q.State(n, Q.QS_C128, stream=stream.cuda_stream)
+    st.load_device(x.data_ptr())
+    st.sync()
+    st.emulate_modmul(0, w, w, c, a, N)          # warm: scratch buffer, code objects
+    st.load_device(x.data_ptr())
+    reps = 10
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record(stream)
+    for r in range(reps):
+        st.emulate_modmul(0, w, w, c, a, N)
+        evs[r + 1].record(stream)
+    stream.synchronize()
+    ms = [evs[r].elapsed_time(evs[r + 1]) for r in range(reps)]
+    avg = float(np.mean(ms))
+    # check one application to the resident input
+    st.load_device(x.data_ptr())
+    st.emulate_modmul(0, w, w, c, a, N)
+    idx = np.random.default_rng(5).integers(0, 1 << n, 4096).astype(np.uint64)
+    got = st.amplitudes(idx)
+    src = O.modmul_source(idx, 0, w, w, c, a, N).astype(np.int64)
+    ref = x[torch.from_numpy(src).to("cuda")].cpu().numpy()
+    exact = bool(np.array_equal(got.view(np.uint64), ref.view(np.uint64)))
+    st.free()
+    del x, v
+    torch.cuda.empty_cache()
+    byts = 2 * 16 * float(1 << n)
+    log("c2 28q modmul: %.3f ms (%.0f GB/s), sampled bit-exact %s" % (avg, byts / avg / 1e6, exact))
+    return {"n_qubits": n, "work_bits": w, "ctrl_bits": c, "a": a, "N": N, "dtype": "c128",
+            "avg_ms": round(avg, 4), "gbs": round(byts / (avg * 1e-3) / 1e9, 1),
+            "frac_of_hbm_peak": round(byts / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": byts, "samples_bit_exact": exact, "samples": int(idx.size)}
+
+
+def config3_mfma32(Q, S):
+    """32 qubits complex64, depth-40 random circuit fused into blocks of up
+    to 6 qubits; 6-qubit blocks run on the FP32 matrix cores (real block
+    form, 512 N flop per launch). Per-block HIP events on the state's
+    stream give the matrix-core kernel's average launch time; the norm is
+    accumulated in FP64. The same generator at 22 qubits (the twin) runs on
+    the GPU in complex64 and on the FP64 oracle for the error."""
+    import torch
+    from oracle import oracle as O
+    n, depth, k = 32, 40, 6
+    gates = S.random_layer_circuit(n, depth, seed=S.SEED_BASE + 3)
+    stream = torch.cuda.Stream()
+    st = Q.State(n, Q.QS_C64, stream=stream.cuda_stream)
+    prog = st.compile(gates, k)
+    nb, ks, moves = prog.info()
+    kinds = [prog.block_kind(b)[0] for b in range(nb)]
+    st.run(prog)                               # warm
+    st.set_zero()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 1)]
+    evs[0].record(stream)
+    for b in range(nb):
+        st.run_range(prog, b, b + 1)
+        evs[b + 1].record(stream)
+    stream.synchronize()
+    ms = np.array([evs[b].elapsed_time(evs[b + 1]) for b in range(nb)])
+    nrm = st.norm2()
+    mfma = [b for b in range(nb) if ks[b] == 6 and kinds[b] == Q.QS_BLOCK_DENSE]
+    N = float(1 << n)
+    t_mfma = float(np.mean(ms[mfma]))
+    flop = 512.0 * N
+    tflops = flop / (t_mfma * 1e-3) / 1e12
+    prog.free()
+    st.free()
+    torch.cuda.empty_cache()
+    # 22-qubit twin against the FP64 oracle
+    nt = 22
+    tg = S.random_layer_circuit(nt, depth, seed=S.SEED_BASE + 3)
+    tw = Q.State(nt, Q.QS_C64)
+    tw.apply_circuit(tg, k)
+    got = tw.get().astype(np.complex128)
+    tw.free()
+    ref = O.apply_circuit(S.zero_state(nt), tg)
+    err = float(np.abs(got - ref).max())
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    fid = float(abs(np.vdot(ref, got)) ** 2)
+    log("c3 32q c64 k=6: %d blocks (%d on matrix cores), %.2f ms per matrix-core launch (%.1f TFLOP/s), "
+        "twin err %.2e" % (nb, len(mfma), t_mfma, tflops, err))
+    return {"n_qubits": n, "depth": depth, "fusion_k": k, "dtype": "c64", "blocks": nb,
+            "mfma_blocks": len(mfma), "circuit_ms": round(float(ms.sum()), 2),
+            "mfma_avg_launch_ms": round(t_mfma, 4),
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
+                         "frac": round(tflops / 157.3, 4), "flop_per_launch": flop,
+                         "hbm_gbs": round(2 * 8 * N / (t_mfma * 1e-3) / 1e9, 1),
+                         "kernel": "k_dense_mfma6 (v_mfma_f32_32x32x2f32, 6-qubit blocks)"},
+            "norm_fp64": nrm,
+            "twin": {"n_qubits": nt, "max_abs_err": err, "rel_l2": rel, "fidelity": fid}}
 
 
 def batch_learned(Q, S):
@@ -177,17 +362,34 @@ def qpe_table(Q, S, ms=(8, 9, 10, 11, 12, 13, 14)):
         t_build = timed(lambda: Q.Unitary(gates, m, 4, stream=stream.cuda_stream).free(), reps=2)
         u = Q.Unitary(gates, m, 4, stream=stream.cuda_stream)
         t_sq = timed(u.square, reps=2)
+        Q.tune_set(Q.QS_TUNE_GEMM_LIB, 1)          # rocBLAS zgemm as the baseline
+        t_sq_lib = timed(u.square, reps=2)
+        Q.tune_set(Q.QS_TUNE_GEMM_LIB, 0)
         u.free()
         u = Q.Unitary(gates, m, 4, stream=stream.cuda_stream)
-        t_eig = timed(u.eig, reps=1)
+        eig_err = None
+        try:
+            t_eig = timed(u.eig, reps=1)
+            resid = u.eig_residual()
+        except Q.QSError as e:              # an unresolved mirror cluster
+            t_eig, resid, eig_err = float("nan"), u.eig_residual(), str(e)
         u.free()
         torch.cuda.empty_cache()
-        out["rows"].append({"m": m, "gates": len(gates), "t_apply_ms": round(t_apply, 4),
-                            "t_build_ms": round(t_build, 4), "t_square_ms": round(t_sq, 4),
-                            "t_eig_ms": round(t_eig, 3),
-                            "crossover_bits_squaring": Q.qpe_crossover_bits(t_apply, t_build, t_sq, True),
-                            "crossover_bits_eig": Q.qpe_crossover_bits(t_apply, t_build, t_eig, False)})
-        log("qpe m=%d: apply %.3f ms, build %.3f ms, square %.3f ms, eig %.1f ms" % (m, t_apply, t_build, t_sq, t_eig))
+        flop = 8.0 * float(1 << m) ** 3
+        row = {"m": m, "gates": len(gates), "t_apply_ms": round(t_apply, 4),
+               "t_build_ms": round(t_build, 4), "t_square_ms": round(t_sq, 4),
+               "square_tflops": round(flop / (t_sq * 1e-3) / 1e12, 2),
+               "square_frac_fp64_peak": round(flop / (t_sq * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+               "t_square_rocblas_ms": round(t_sq_lib, 4),
+               "t_eig_ms": round(t_eig, 3), "eig_residual": resid,
+               "crossover_bits_squaring": Q.qpe_crossover_bits(t_apply, t_build, t_sq, True),
+               "crossover_bits_eig": (Q.qpe_crossover_bits(t_apply, t_build, t_eig, False)
+                                      if eig_err is None else None)}
+        if eig_err is not None:
+            row["eig_error"] = eig_err
+        out["rows"].append(row)
+        log("qpe m=%d: apply %.3f ms, build %.3f ms, square %.3f ms (%.1f TFLOP/s; rocBLAS %.3f ms), eig %.1f ms"
+            % (m, t_apply, t_build, t_sq, row["square_tflops"], t_sq_lib, t_eig))
     m, b = 10, 10
     gates = S.tfim_trotter_step(m)
     n = m + b
@@ -312,11 +514,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parts", default="all",
-                    help="all | fused | batch | qpe | arith (profiling runs: one part only)")
+                    help="all | fused | batch | qpe | arith | configs (profiling runs: one part only)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain part")
     ap.add_argument("--no-qpe", action="store_true", help="skip the phase-estimation part")
     ap.add_argument("--no-arith", action="store_true", help="skip the multiplication/division part")
     ap.add_argument("--arith-ms", default="4,6,8,10", help="register widths m of the multiplication/division part")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 16-qubit gate-level, 28-qubit modmul and 32-qubit matrix-core parts")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state-vector path is not sharded "
@@ -333,6 +537,12 @@ def main():
         return
     if args.parts == "qpe":
         print(json.dumps({"parts": "qpe", "phase_estimation": qpe_table(Q, S)}), flush=True)
+        return
+    if args.parts == "configs":
+        print(json.dumps({"parts": "configs", "configs": {
+            "c0_16q_gate_level": config0_gate_level(Q, S),
+            "c2_28q_modmul": config2_modmul28(Q, S),
+            "c3_32q_c64_k6_mfma": config3_mfma32(Q, S)}}), flush=True)
         return
     if args.parts == "arith":
         ms = tuple(int(v) for v in args.arith_ms.split(","))
@@ -357,12 +567,18 @@ def main():
         normal /= torch.linalg.vector_norm(normal)
     stream.synchronize()
 
-    # plan once to know the block count (the step plans again)
-    _, blocks = Q.plan_fusion(gates, n, MAX_K)
-    n_blocks = len(blocks)
+    # compile once to learn the blocks (the step compiles again): kinds,
+    # widths and the bytes each block must move
+    prog0 = st.compile(gates, MAX_K)
+    n_blocks, block_k, amp_moves = prog0.info()
+    block_kind = [prog0.block_kind(b) for b in range(n_blocks)]
+    prog0.free()
+    dense4 = [b for b in range(n_blocks) if block_kind[b][0] == Q.QS_BLOCK_DENSE and block_k[b] == 4]
     parts_all = args.parts == "all"
 
     ev = {}
+    blk_ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_blocks + 1)]
+    blk_ms = []
 
     def mark(name):
         e = torch.cuda.Event(enable_timing=True)
@@ -375,7 +591,12 @@ def main():
         mark("init")
         prog = st.compile(gates, MAX_K)
         mark("compile")
-        st.run(prog)
+        # one launch group per block, with events between them: the dense
+        # sweep's own launch time is read off these
+        blk_ev[0].record(stream)
+        for b in range(n_blocks):
+            st.run_range(prog, b, b + 1)
+            blk_ev[b + 1].record(stream)
         mark("fused")
         z0 = st.expectation(z_mask=1).real
         nrm = st.norm2()
@@ -409,6 +630,7 @@ def main():
         names = list(ev.keys())
         for a, b in zip(names[:-1], names[1:]):
             part_ms.setdefault(b, []).append(ev[a].elapsed_time(ev[b]))
+        blk_ms.append([blk_ev[b].elapsed_time(blk_ev[b + 1]) for b in range(n_blocks)])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -416,7 +638,7 @@ def main():
 
     bytes_part = {
         "init": amp * N,
-        "fused": n_blocks * 2 * amp * N,
+        "fused": amp_moves * amp,
         "reduce": 2 * amp * N,
     }
     if parts_all:
@@ -430,16 +652,28 @@ def main():
     total_bytes = sum(bytes_part.values())
     value = total_bytes / (ms_per_step * 1e-3) / 1e9
 
-    # dominant kernel: the fused block sweep (one launch per block of up to
-    # k = 4 qubits; each moves the whole state once)
-    sweep_ms = part_ms["fused"] / n_blocks
+    # dominant kernel: the dense 4-qubit block sweep (k_dense_tile<double,4>,
+    # the tuned complex128 path for 2- to 4-qubit blocks); each launch reads
+    # and writes the whole state once. Its average launch time comes from
+    # the per-block events of the timed steps.
+    blk = np.array(blk_ms)                        # steps x blocks
+    sweep_ms = float(blk[:, dense4].mean())
     achieved = 2 * amp * N / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "fused block sweeps, blocks of up to 4 qubits (k_dense_tile, the tuned default for "
-                          "complex128 blocks of 2 to 4 qubits, and k_diag for diagonal blocks), average over "
-                          "the step's launches",
+                "kernel": "k_dense_tile<double,4>: dense 4-qubit fused-block sweep, complex128, "
+                          "average over the %d such launches per step" % len(dense4),
                 "avg_launch_ms": round(sweep_ms, 4), "bytes_per_launch": 2 * amp * N}
+    kinds_count = {"dense": sum(1 for k, _ in block_kind if k == Q.QS_BLOCK_DENSE),
+                   "diagonal": sum(1 for k, _ in block_kind if k == Q.QS_BLOCK_DIAGONAL),
+                   "identity": sum(1 for k, _ in block_kind if k == Q.QS_BLOCK_IDENTITY)}
+    diag_b = [b for b in range(n_blocks) if block_kind[b][0] == Q.QS_BLOCK_DIAGONAL]
+    fused_detail = {"blocks": n_blocks, "kinds": kinds_count,
+                    "dense_k4_launches": len(dense4),
+                    "block_widths": {str(k): int(np.sum(np.asarray(block_k) == k)) for k in range(1, MAX_K + 1)},
+                    "diagonal_blocks": [{"k": int(block_k[b]), "changed_fraction": block_kind[b][1],
+                                         "ms": round(float(blk[:, b].mean()), 4)} for b in diag_b],
+                    "amp_moves_per_run": amp_moves}
 
     # at-scale consistency (untimed): gate-level QFT then emulated inverse
     # returns the input; sampled amplitudes compared with the resident input
@@ -476,6 +710,11 @@ def main():
     arith = None
     if not args.no_arith and parts_all:
         arith = arith_table(Q, S, tuple(int(v) for v in args.arith_ms.split(",")))
+    configs = None
+    if not args.no_configs and parts_all:
+        configs = {"c0_16q_gate_level": config0_gate_level(Q, S),
+                   "c2_28q_modmul": config2_modmul28(Q, S),
+                   "c3_32q_c64_k6_mfma": config3_mfma32(Q, S)}
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) starts")
@@ -502,6 +741,7 @@ def main():
                    "parts": args.parts},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fused_detail": fused_detail,
         "breakdown_ms": {k: round(v, 3) for k, v in part_ms.items()},
         "breakdown_gbs": {k: round(bytes_part[k] / (part_ms[k] * 1e-3) / 1e9, 1)
                           for k in bytes_part if k in part_ms and part_ms[k] > 0},
@@ -510,6 +750,7 @@ def main():
         "batched_learned": batched,
         "phase_estimation": qpe,
         "arithmetic": arith,
+        "configs": configs,
     }
     print(json.dumps(out), flush=True)
 

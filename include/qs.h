@@ -190,11 +190,28 @@ int qs_plan_fusion(const qs_circuit *c, int n_qubits, int max_k, int *n_blocks,
 int qs_compile(qs_handle h, const qs_circuit *c, int max_k, qs_program *out);
 
 /* Number of blocks and, if block_k != NULL, their widths; amp_moves_per_run:
- * amplitude reads plus writes one run makes (every block reads and writes
- * all 2^n amplitudes). A program has no dtype of its own, so multiply by the
- * amplitude size of the handle it runs on (16 B complex128, 8 B complex64)
- * for the algorithmic HBM bytes. */
+ * the amplitude reads plus writes one run must make. A dense block reads and
+ * writes all 2^n amplitudes; a diagonal block only those whose entry is not
+ * exactly one (a conditional phase shift changes only the amplitudes that
+ * carry its phase, Sec. III-B), and a block whose diagonal is all ones
+ * nothing. A program has no dtype of its own, so multiply by the amplitude
+ * size of the handle it runs on (16 B complex128, 8 B complex64) for the
+ * algorithmic HBM bytes. When a diagonal block has a target inside a
+ * 128-byte line the kernel rewrites whole lines, so it moves more than this
+ * count. */
 int qs_program_info(qs_program p, int *n_blocks, int *block_k, double *amp_moves_per_run);
+
+/* How block b runs (Sec. II sweep vs Sec. III-B's touched-only phases):
+ * *kind = QS_BLOCK_DENSE (one sweep of the whole state), QS_BLOCK_DIAGONAL
+ * (only the target patterns whose entry is not one are swept: one phase
+ * launch for a single such entry, else one launch per distinct pattern of
+ * the targets above the 128-byte line, or one elementwise pass when those
+ * launches would touch more than half the state) or QS_BLOCK_IDENTITY
+ * (nothing is launched). *changed_fraction: the fraction of amplitudes the
+ * block changes (1 for dense blocks). Either output may be NULL.
+ * QS_EINVAL for a NULL program or b outside [0, n_blocks). */
+enum qs_block_kind { QS_BLOCK_DENSE = 0, QS_BLOCK_DIAGONAL = 1, QS_BLOCK_IDENTITY = 2 };
+int qs_program_block_kind(qs_program p, int b, int *kind, double *changed_fraction);
 
 /* Copy the composed FP64 matrix of block b (2^(2k+1) doubles) and its
  * ascending qubit list (k ints) to the host. */
@@ -202,6 +219,11 @@ int qs_program_block(qs_program p, int b, double *matrix_out, int *qubits_out);
 
 /* Enqueue one run of the program on the handle. */
 int qs_run_program(qs_handle h, qs_program p);
+
+/* Enqueue blocks [b0, b1) of the program, in order (0 <= b0 <= b1 <=
+ * n_blocks, else QS_EINVAL): running consecutive ranges equals one run.
+ * Lets a caller put events between blocks to time each launch. */
+int qs_run_program_range(qs_handle h, qs_program p, int b0, int b1);
 
 int qs_program_free(qs_program p);
 
@@ -391,6 +413,17 @@ typedef struct qs_mlp_t *qs_mlp;
 int qs_mlp_create(const float *params, uint64_t seed, void *hip_stream, qs_mlp *out);
 int qs_mlp_get_params(qs_mlp m, float *params);
 int qs_mlp_set_norm(qs_mlp m, const float *mean, const float *inv_std);
+/* Range of the raw features over the training rows (QS_N_FEATURES floats
+ * each, lo <= hi, finite; a bound of +-3e38 turns the check off for that
+ * feature). A segment with a feature more than 5% of its range outside it is
+ * planned by the heuristic under QS_POLICY_LEARNED. lo = hi = NULL clears
+ * the range (no check). QS_EINVAL for one NULL bound or a bad range. */
+int qs_mlp_set_range(qs_mlp m, const float *lo, const float *hi);
+/* Segment counts of the last qs_batch_choose(QS_POLICY_LEARNED) with this
+ * model, counts[4]: planned by the model, fallen back for a feature outside
+ * the range, for a non-finite prediction, and for a predicted gain below the
+ * margin. */
+int qs_mlp_choose_stats(qs_mlp m, int *counts);
 /* y[n][4] for x[n][24] (host arrays). */
 int qs_mlp_forward(qs_mlp m, int n, const float *x, float *y);
 /* Loss sum(mask (y - t)^2) / sum(mask) and its gradient (6020 floats). */
@@ -409,7 +442,13 @@ int qs_mlp_free(qs_mlp m);
  *   QS_POLICY_HEURISTIC: arithmetic emulated (Sec. III-A, IV-B); QFT
  *     emulated when Eq. (1) (one device, no exchange) beats Eq. (2); gate
  *     lists fused at the width with the lowest roofline estimate;
- *   QS_POLICY_LEARNED: the option with the smallest predicted time. */
+ *   QS_POLICY_LEARNED: the option with the smallest predicted time, unless
+ *     the heuristic's rules (above; Eqs. (1), (2)) are the fallback for the
+ *     segment: a feature outside the model's training range
+ *     (qs_mlp_set_range), a non-finite prediction, or a predicted gain over
+ *     the heuristic's own option below 5% (0.05 in natural-log time). Only
+ *     the plan differs between policies: every option gives the same state
+ *     up to rounding. */
 enum qs_policy { QS_POLICY_HEURISTIC = 0, QS_POLICY_LEARNED = 1, QS_POLICY_FIXED_K2 = 2,
                  QS_POLICY_FIXED_K4 = 3, QS_POLICY_FIXED_K6 = 4 };
 int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options);
@@ -449,6 +488,16 @@ int qs_unitary_free(qs_unitary u);
  * caller's. */
 int qs_emulate_qpe_powers(qs_handle h, const qs_circuit *c, int m, int ctrl_lo, int b, int max_k);
 
+/* The crossover precision of Table 2 (host only, no GPU): the smallest
+ * b in [1, bmax] for which a simulator's 2^b - 1 applications of U
+ * (t_apply each) cost at least the emulator's build plus its per-bit
+ * squarings (per_bit != 0: t_build + b t_op) or its one eigendecomposition
+ * (per_bit == 0: t_build + t_op). This rule reproduces both crossover rows
+ * of Table 2 from its timing rows. *out_bits = 0 if no b up to bmax
+ * qualifies. QS_EINVAL for a NULL output, a time that is negative or not
+ * finite, or bmax outside [1, 1000]. */
+int qs_qpe_crossover_bits(double t_apply, double t_build, double t_op, int per_bit, int bmax, int *out_bits);
+
 /* The eigensolver route of Sec. III-C: U = V diag(e^(i theta)) V^dagger,
  * after which every controlled power costs the same. The library's
  * eigensolver is Hermitian (rocSOLVER zheevd), so it is given
@@ -456,12 +505,20 @@ int qs_emulate_qpe_powers(qs_handle h, const qs_circuit *c, int m, int ctrl_lo, 
  * has U's eigenvectors; each pair of neighbouring eigenvectors is then
  * rotated by the exact eigenvectors of its 2 x 2 block of V^dagger U V (even
  * pairs, then odd pairs), which separates eigenphases that H's eigenvalues
- * cos(theta) + beta sin(theta) confuse (mirror images about atan(beta)); a
- * cluster of three or more such phases is resolved only pairwise. theta_k is
- * the argument of the final diagonal, in (-pi, pi]. Device memory: three
- * more 2^m x 2^m matrices during the call, V kept. Synchronous; QS_EDEVICE
- * if the eigensolver does not converge. */
+ * cos(theta) + beta sin(theta) confuse (mirror images about atan(beta)). theta_k
+ * is the argument of the final diagonal, in (-pi, pi]. The result is checked:
+ * the largest off-diagonal magnitude of V^dagger U V must not exceed 1e-10
+ * (U's 2-norm is 1). A cluster of three or more confused phases (a phase
+ * with a multiplicity plus its mirror image) is not separated by the pair
+ * passes and fails this check: QS_EUNSUPPORTED, no decomposition is kept,
+ * and the squaring route (qs_emulate_qpe_powers) still applies. Device
+ * memory: three more 2^m x 2^m matrices during the call, V kept.
+ * Synchronous; QS_EDEVICE if the eigensolver does not converge. */
 int qs_unitary_eig(qs_unitary u);
+/* The largest off-diagonal magnitude of V^dagger U V measured by the last
+ * qs_unitary_eig (also after it failed the check). QS_EINVAL for NULL
+ * arguments or before any qs_unitary_eig. */
+int qs_unitary_eig_residual(qs_unitary u, double *offdiag);
 /* Copy the eigenphases (2^m doubles) and/or V (2^m x 2^m complex128,
  * row-major as qs_unitary_get; column k belongs to theta_k); either pointer
  * may be NULL. QS_EINVAL before qs_unitary_eig. */
@@ -513,6 +570,10 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     register and LDS-staged dense sweeps: bit 0 nontemporal (streaming)
  *     stores, bit 1 nontemporal loads; 0 plain accesses.
  *   QS_TUNE_FFT_NT (dtype, -, -, n bucket): the same for the FFT passes.
+ *   QS_TUNE_GEMM_LIB (-, -, -, -): complex products of the dense-unitary
+ *     route (squaring, controlled powers, the eigensolver route's
+ *     products): 0 the library's own matrix-core kernel, 1 rocBLAS (a
+ *     baseline for timing).
  * Index dimensions: dtype QS_C64/QS_C128; k 0..QS_MAX_K; class
  * QS_TCLS_* of the lowest target; n bucket 0 (n < 22), 1 (22..27),
  * 2 (n >= 28). Dimensions a parameter ignores are read at index 0.
@@ -522,7 +583,7 @@ enum qs_tune_param { QS_TUNE_SWEEP_PATH = 0, QS_TUNE_SWEEP_WG_PER_CU = 1, QS_TUN
                      QS_TUNE_FFT_LDS_KB = 3, QS_TUNE_MFMA_WG_PER_CU = 4,
                      QS_TUNE_BATCH_GANG_SHARE = 5, QS_TUNE_BATCH_BARRIER_AMPS = 6,
                      QS_TUNE_FFT_KERNEL = 7, QS_TUNE_SWEEP_NT = 8, QS_TUNE_FFT_NT = 9,
-                     QS_TUNE_COUNT = 10 };
+                     QS_TUNE_GEMM_LIB = 10, QS_TUNE_COUNT = 11 };
 /* Target classes: lowest target inside a 128-byte line, inside a wave's
  * 64 consecutive amplitudes, or above bit 5. */
 enum qs_tune_class { QS_TCLS_SUBLINE = 0, QS_TCLS_SUBWAVE = 1, QS_TCLS_HIGH = 2 };

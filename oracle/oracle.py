@@ -41,6 +41,8 @@ def lib():
             build_oracle.build()
         L = C.CDLL(path)
         P = C.c_void_p
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = C.c_int
         L.or_table1.argtypes = [C.c_int, C.c_double, P]
         L.or_apply_gate.argtypes = [P, C.c_int, C.c_int, P, P, C.c_uint64, C.c_uint64]
         L.or_apply_circuit.argtypes = [P, C.c_int, C.c_int, P, P, P, P, P]
@@ -82,6 +84,12 @@ class OracleError(RuntimeError):
 def _chk(rc):
     if rc != 0:
         raise OracleError("oracle rejected its arguments (rc=%d)" % rc)
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the C oracle's loops (0 keeps the current count);
+    returns the count in effect."""
+    return int(lib().or_set_threads(int(n)))
 
 
 # ---------------------------------------------------------------------------

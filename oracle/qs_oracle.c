@@ -26,6 +26,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -35,6 +38,20 @@ typedef double complex cplx;
 /* ---------------------------------------------------------------------- */
 /* Table 1 gate constants, written out from the table.                     */
 /* ---------------------------------------------------------------------- */
+/* Number of host threads the OpenMP loops below use (a timing control for
+ * the CPU baseline; results do not depend on it). Returns the count in
+ * effect. */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 void or_table1(int which, double theta, double *out /* 2^k x 2^k interleaved */)
 {
     /* which: 0 X, 1 Y, 2 Z, 3 H, 4 S, 5 T, 6 Rz(theta), 7 CNOT, 8 CR(theta) */

@@ -200,6 +200,30 @@ __global__ __launch_bounds__(1024) void k_copy16(const U4 *__restrict__ src, U4 
     if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Blocks [b0, b1) of a compiled program: dense blocks sweep the whole state,
+// diagonal blocks only the amplitudes whose entry is not one.
+int run_blocks(qs_state *h, const qs_program_t *p, int b0, int b1)
+{
+    for (int b = b0; b < b1; ++b) {
+        GateDesc d;
+        d.k = p->k[size_t(b)];
+        for (int m = 0; m < d.k; ++m) d.targets[m] = p->qubits[size_t(b)][size_t(m)];
+        const void *dm = (h->dtype == QS_C128)
+                             ? static_cast<const void *>(p->dmats + p->mat_off[size_t(b)])
+                             : static_cast<const void *>(p->dmats32 + p->mat_off[size_t(b)]);
+        int rc;
+        if (p->diagonal[size_t(b)]) {
+            d.cls = GC_DIAG;
+            rc = launch_diag_block(h, d, dm, 1 << d.k, p->hdiag[size_t(b)].data());
+        } else {
+            d.cls = GC_DENSE;
+            rc = launch_dense(h, d, dm);
+        }
+        if (rc) return rc;
+    }
+    return QS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -516,6 +540,25 @@ int qs_compile(qs_handle h, const qs_circuit *c, int max_k, qs_program *out)
         if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
             return bail(hip_fail(e, "compose"));
     }
+    // Diagonal blocks keep their composed diagonal on the host: the run
+    // sweeps only the amplitudes whose entry is not one.
+    pr->hdiag.resize(size_t(pr->n_blocks));
+    pr->changed.assign(size_t(pr->n_blocks), 1.0);
+    for (int b = 0; b < pr->n_blocks; ++b) {
+        if (!pr->diagonal[size_t(b)]) continue;
+        const size_t D = size_t(1) << pr->k[size_t(b)];
+        std::vector<double> full(2 * D * D);
+        hipError_t e = hipMemcpy(full.data(), pr->dmats + pr->mat_off[size_t(b)], full.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipMemcpy(diagonal block)"));
+        auto &hd = pr->hdiag[size_t(b)];
+        hd.resize(2 * D);
+        for (size_t j = 0; j < D; ++j) {
+            hd[2 * j] = full[2 * (j * D + j)];
+            hd[2 * j + 1] = full[2 * (j * D + j) + 1];
+        }
+        pr->changed[size_t(b)] = diag_changed_fraction(hd.data(), pr->k[size_t(b)]);
+    }
     cleanup();
     *out = pr;
     return QS_OK;
@@ -528,8 +571,36 @@ int qs_program_info(qs_program p, int *n_blocks, int *block_k, double *amp_moves
     if (n_blocks) *n_blocks = p->n_blocks;
     if (block_k)
         for (int b = 0; b < p->n_blocks; ++b) block_k[b] = p->k[size_t(b)];
-    if (amp_moves_per_run) *amp_moves_per_run = double(p->n_blocks) * 2.0 * std::ldexp(1.0, p->n);
+    if (amp_moves_per_run) {
+        // dense blocks read and write every amplitude; diagonal blocks only
+        // the ones whose entry is not one
+        double f = 0.0;
+        for (int b = 0; b < p->n_blocks; ++b) f += p->changed[size_t(b)];
+        *amp_moves_per_run = f * 2.0 * std::ldexp(1.0, p->n);
+    }
     return QS_OK;
+}
+
+int qs_program_block_kind(qs_program p, int b, int *kind, double *changed_fraction)
+{
+    clear_error();
+    if (!p) return fail(QS_EINVAL, "NULL program");
+    if (b < 0 || b >= p->n_blocks) return fail(QS_EINVAL, "block %d outside [0, %d)", b, p->n_blocks);
+    const double f = p->changed[size_t(b)];
+    if (kind) *kind = !p->diagonal[size_t(b)] ? QS_BLOCK_DENSE : (f == 0.0 ? QS_BLOCK_IDENTITY : QS_BLOCK_DIAGONAL);
+    if (changed_fraction) *changed_fraction = f;
+    return QS_OK;
+}
+
+int qs_run_program_range(qs_handle h, qs_program p, int b0, int b1)
+{
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!p) return fail(QS_EINVAL, "NULL program");
+    if (p->n != h->n) return fail(QS_EINVAL, "program built for %d qubits, state has %d", p->n, h->n);
+    if (b0 < 0 || b1 < b0 || b1 > p->n_blocks)
+        return fail(QS_EINVAL, "block range [%d, %d) outside [0, %d]", b0, b1, p->n_blocks);
+    return run_blocks(h, p, b0, b1);
 }
 
 int qs_program_block(qs_program p, int b, double *matrix_out, int *qubits_out)
@@ -554,24 +625,7 @@ int qs_run_program(qs_handle h, qs_program p)
     if (int rc = check_handle(h)) return rc;
     if (!p) return fail(QS_EINVAL, "NULL program");
     if (p->n != h->n) return fail(QS_EINVAL, "program built for %d qubits, state has %d", p->n, h->n);
-    for (int b = 0; b < p->n_blocks; ++b) {
-        GateDesc d;
-        d.k = p->k[size_t(b)];
-        for (int m = 0; m < d.k; ++m) d.targets[m] = p->qubits[size_t(b)][size_t(m)];
-        const void *dm = (h->dtype == QS_C128)
-                             ? static_cast<const void *>(p->dmats + p->mat_off[size_t(b)])
-                             : static_cast<const void *>(p->dmats32 + p->mat_off[size_t(b)]);
-        int rc;
-        if (p->diagonal[size_t(b)]) {
-            d.cls = GC_DIAG;
-            rc = launch_diag(h, d, dm, 1 << d.k);
-        } else {
-            d.cls = GC_DENSE;
-            rc = launch_dense(h, d, dm);
-        }
-        if (rc) return rc;
-    }
-    return QS_OK;
+    return run_blocks(h, p, 0, p->n_blocks);
 }
 
 int qs_program_free(qs_program p)

@@ -183,6 +183,12 @@ struct qs_mlp_t {
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     float *mean = nullptr, *istd = nullptr;
     int adam_t = 0;
+    // raw feature range of the training rows (host); unset: no range check
+    bool have_range = false;
+    float lo[QS_N_FEATURES] = {0}, hi[QS_N_FEATURES] = {0};
+    // segments of the last learned choice: [learned, out of range,
+    // non-finite prediction, gain below the margin]
+    int choose_counts[4] = {0, 0, 0, 0};
     // work buffers sized for `cap` rows
     int cap = 0;
     float *x = nullptr, *t = nullptr, *mask = nullptr, *xs = nullptr, *a1 = nullptr, *a2 = nullptr,
@@ -403,6 +409,32 @@ int qs_mlp_train(qs_mlp m, int n, const float *x, const float *t, const float *m
     return QS_OK;
 }
 
+int qs_mlp_set_range(qs_mlp m, const float *lo, const float *hi)
+{
+    clear_error();
+    if (!m) return fail(QS_EINVAL, "NULL model");
+    if (!lo && !hi) {
+        m->have_range = false;
+        return QS_OK;
+    }
+    if (!lo || !hi) return fail(QS_EINVAL, "NULL range bound");
+    for (int i = 0; i < kIn; ++i)
+        if (!std::isfinite(lo[i]) || !std::isfinite(hi[i]) || lo[i] > hi[i])
+            return fail(QS_EINVAL, "feature %d: bad range [%g, %g]", i, double(lo[i]), double(hi[i]));
+    std::copy(lo, lo + kIn, m->lo);
+    std::copy(hi, hi + kIn, m->hi);
+    m->have_range = true;
+    return QS_OK;
+}
+
+int qs_mlp_choose_stats(qs_mlp m, int *counts)
+{
+    clear_error();
+    if (!m || !counts) return fail(QS_EINVAL, "NULL argument");
+    std::copy(m->choose_counts, m->choose_counts + 4, counts);
+    return QS_OK;
+}
+
 int qs_mlp_free(qs_mlp m)
 {
     clear_error();
@@ -438,6 +470,37 @@ double fused_cost(double blocks, int k, int n)
     return blocks * (2.0 * 8.0 * N / kBmem + 8.0 * std::ldexp(1.0, k) * N / kF32);
 }
 
+// The paper's rules for one segment (QS_POLICY_HEURISTIC): arithmetic is
+// always emulated (Sec. III-A, IV-B); a QFT is emulated when Eq. (1) with one
+// device and no exchange does not exceed Eq. (2); a gate list takes the
+// fusion width with the lowest roofline estimate.
+int heuristic_option(int kind, int n, const float *fs)
+{
+    if (kind == QS_SEG_MODMUL) return QS_PLAN_EMULATE;
+    if (kind == QS_SEG_QFT) {
+        const double N = std::ldexp(1.0, n), m = double(fs[14]);
+        const double t_fft = 5.0 * N * m / (kEffFft * kF32Peak);
+        const double t_qft = 4.0 * N * m * m / kBmem;
+        if (t_fft <= t_qft) return QS_PLAN_EMULATE;
+    }
+    int best = 0;
+    double bc = 0.0;
+    for (int o = 0; o < 3; ++o) {
+        const double c = fused_cost(blocks_from_feature(fs[17 + o]), 2 + 2 * o, n);
+        if (o == 0 || c < bc) {
+            bc = c;
+            best = o;
+        }
+    }
+    return best;
+}
+
+// A learned choice departs from the heuristic only when the model predicts
+// it at least this much faster (natural-log time, ~5%).
+constexpr float kLearnedMargin = 0.05f;
+// Features may lie this fraction of the training range outside it.
+constexpr float kRangeSlack = 0.05f;
+
 }  // namespace
 
 extern "C" int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *options)
@@ -453,51 +516,52 @@ extern "C" int qs_batch_choose(qs_batch b, int policy, qs_mlp model, int *option
     if (int rc = qs_batch_segment_info(b, kind.data(), circ.data(), nq.data())) return rc;
     std::vector<float> f(size_t(ns) * QS_N_FEATURES);
     if (int rc = qs_batch_features(b, f.data())) return rc;
-    if (policy == QS_POLICY_LEARNED) {
-        std::vector<float> y(size_t(ns) * 4);
-        if (int rc = qs_mlp_forward(model, ns, f.data(), y.data())) return rc;
-        for (int s = 0; s < ns; ++s) {
-            const int nopt = kind[size_t(s)] == QS_SEG_GATES ? 3 : 4;
-            int best = 0;
-            for (int o = 1; o < nopt; ++o)
-                if (y[size_t(s) * 4 + size_t(o)] < y[size_t(s) * 4 + size_t(best)]) best = o;
-            options[s] = best;
-        }
+    if (policy == QS_POLICY_FIXED_K2 || policy == QS_POLICY_FIXED_K4 || policy == QS_POLICY_FIXED_K6) {
+        for (int s = 0; s < ns; ++s)
+            options[s] = kind[size_t(s)] == QS_SEG_GATES ? policy - QS_POLICY_FIXED_K2 : QS_PLAN_EMULATE;
         return QS_OK;
     }
+    for (int s = 0; s < ns; ++s)
+        options[s] = heuristic_option(kind[size_t(s)], nq[size_t(s)], f.data() + size_t(s) * QS_N_FEATURES);
+    if (policy == QS_POLICY_HEURISTIC) return QS_OK;
+    // learned: the predicted fastest option, with the heuristic as fallback
+    // for segments the model has not seen the like of (features outside the
+    // training range), cannot rate (non-finite outputs) or rates as no
+    // clear gain over the heuristic's own option
+    std::vector<float> y(size_t(ns) * 4);
+    if (int rc = qs_mlp_forward(model, ns, f.data(), y.data())) return rc;
+    int cnt[4] = {0, 0, 0, 0};
     for (int s = 0; s < ns; ++s) {
         const float *fs = f.data() + size_t(s) * QS_N_FEATURES;
-        const int n = nq[size_t(s)];
-        if (policy == QS_POLICY_FIXED_K2 || policy == QS_POLICY_FIXED_K4 || policy == QS_POLICY_FIXED_K6) {
-            options[s] = kind[size_t(s)] == QS_SEG_GATES ? policy - QS_POLICY_FIXED_K2 : QS_PLAN_EMULATE;
+        const float *ys = y.data() + size_t(s) * 4;
+        const int nopt = kind[size_t(s)] == QS_SEG_GATES ? 3 : 4;
+        bool finite = true;
+        for (int o = 0; o < nopt; ++o) finite = finite && std::isfinite(ys[o]);
+        if (!finite) {
+            ++cnt[2];
             continue;
         }
-        // heuristic: arithmetic is always emulated; the QFT compares Eq. (1)
-        // (one device, no exchange) with Eq. (2); gate lists take the fusion
-        // width with the lowest roofline estimate
-        if (kind[size_t(s)] == QS_SEG_MODMUL) {
-            options[s] = QS_PLAN_EMULATE;
-            continue;
-        }
-        if (kind[size_t(s)] == QS_SEG_QFT) {
-            const double N = std::ldexp(1.0, n), m = double(fs[14]);
-            const double t_fft = 5.0 * N * m / (kEffFft * kF32Peak);
-            const double t_qft = 4.0 * N * m * m / kBmem;
-            if (t_fft <= t_qft) {
-                options[s] = QS_PLAN_EMULATE;
-                continue;
+        bool inside = true;
+        if (model->have_range)
+            for (int i = 0; i < QS_N_FEATURES && inside; ++i) {
+                const float slack = kRangeSlack * (model->hi[i] - model->lo[i]);
+                inside = fs[i] >= model->lo[i] - slack && fs[i] <= model->hi[i] + slack;
             }
+        if (!inside) {
+            ++cnt[1];
+            continue;
         }
         int best = 0;
-        double bc = 0.0;
-        for (int o = 0; o < 3; ++o) {
-            const double c = fused_cost(blocks_from_feature(fs[17 + o]), 2 + 2 * o, n);
-            if (o == 0 || c < bc) {
-                bc = c;
-                best = o;
-            }
+        for (int o = 1; o < nopt; ++o)
+            if (ys[o] < ys[best]) best = o;
+        const int heur = options[s];
+        if (best != heur && ys[heur] - ys[best] < kLearnedMargin) {
+            ++cnt[3];
+            continue;
         }
         options[s] = best;
+        ++cnt[0];
     }
+    std::copy(cnt, cnt + 4, model->choose_counts);
     return QS_OK;
 }

@@ -29,12 +29,15 @@
 // once: the slice of the state whose control register holds c gets
 // V diag(e^(i c theta)) V^dagger, two GEMMs over the state viewed as a
 // 2^m x 2^(n-m) matrix and one elementwise phase.
+#include <cmath>
+
 #include "qs_internal.h"
 
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <vector>
 #include <cstring>
 
 using namespace qs;
@@ -51,6 +54,7 @@ struct qs_unitary_t {
     float *v32 = nullptr;    // complex64 copy of v
     bool v32_valid = false;
     bool eig_valid = false;
+    double eig_offdiag = -1.0;  // max |(V^dagger U V)_ij|, i != j, after the last qs_unitary_eig
     size_t dim() const { return size_t(1) << m; }
     size_t elems() const { return dim() * dim(); }
 };
@@ -58,6 +62,9 @@ struct qs_unitary_t {
 namespace {
 
 constexpr int kMaxUnitaryQubits = 15;   // 2^30 entries, 16 GiB per matrix
+// Largest off-diagonal magnitude of V^dagger U V accepted from the
+// eigensolver route (U is unitary, so its 2-norm is 1).
+constexpr double kEigResidualTol = 1e-10;
 
 rocblas_handle blas(int &rc)
 {
@@ -185,6 +192,27 @@ __global__ void k_pair_apply(double2 *__restrict__ V, const double2 *__restrict_
     }
 }
 
+// Largest off-diagonal magnitude of D (d x d): per-block maxima into part[]
+// (256-thread blocks), reduced on the host.
+__global__ __launch_bounds__(256) void k_offdiag_max(const double2 *__restrict__ D, int m, double *__restrict__ part)
+{
+    const uint64_t d = 1ull << m, count = d * d;
+    double mx = 0.0;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        if ((i & (d - 1)) == (i >> m)) continue;
+        mx = fmax(mx, sqrt(cabs2(D[i])));
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 __global__ void k_diag_arg(const double2 *__restrict__ D, double *__restrict__ theta, int m)
 {
     const uint64_t d = 1ull << m;
@@ -215,6 +243,18 @@ __global__ void k_eig_phase(C2 *__restrict__ Y, const double *__restrict__ theta
 unsigned grid_of(uint64_t items)
 {
     return unsigned(std::max<uint64_t>(1, std::min<uint64_t>((items + 255) / 256, 1ull << 20)));
+}
+
+// The complex products of this route run on the library's own matrix-core
+// kernel (cgemm.hip); QS_TUNE_GEMM_LIB = 1 selects rocBLAS instead, kept as
+// a timed baseline.
+bool use_blas() { return tune_value(QS_TUNE_GEMM_LIB, 0, 0, 0, 0) == 1; }
+
+ColMap plain_cols(uint64_t ld)
+{
+    ColMap c;
+    c.ld = ld;
+    return c;
 }
 
 int check_gates(const qs_circuit *c, int m)
@@ -284,9 +324,18 @@ int qs_unitary_square(qs_unitary u)
     clear_error();
     if (!u) return fail(QS_EINVAL, "NULL unitary");
     int rc = QS_OK;
+    if (!u->tmp) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->tmp), u->elems() * 16));
+    if (!use_blas()) {
+        const int d = int(u->dim());
+        if ((rc = launch_cgemm(u->stream, QS_C128, false, u->u, d, d, d, u->u, plain_cols(uint64_t(d)), u->tmp,
+                               plain_cols(uint64_t(d)), uint64_t(d))))
+            return rc;
+        std::swap(u->u, u->tmp);
+        u->u32_valid = false;
+        return QS_OK;
+    }
     rocblas_handle b = blas(rc);
     if (rc) return rc;
-    if (!u->tmp) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->tmp), u->elems() * 16));
     if ((rc = blas_check(rocblas_set_stream(b, u->stream), "rocblas_set_stream"))) return rc;
     const rocblas_int d = rocblas_int(u->dim());
     const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
@@ -325,11 +374,50 @@ int qs_apply_controlled_unitary(qs_handle h, qs_unitary u, int ctrl)
     if (ctrl - m > 30 || h->n - ctrl - 1 > 30)
         return fail(QS_EUNSUPPORTED, "batched product dimensions exceed 32-bit BLAS sizes");
     int rc = QS_OK;
+    if ((rc = ensure_scratch(h))) return rc;
+    // the products run on the handle's stream; the unitary must be ready there
+    if (u->stream != h->stream) QS_HIP(hipStreamSynchronize(u->stream));
+    const void *ua = u->u;
+    if (h->dtype == QS_C64) {
+        if (!u->u32) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->u32), u->elems() * 8));
+        if (!u->u32_valid) {
+            hipLaunchKernelGGL(k_cast_u, dim3(grid_of(2 * u->elems())), dim3(256), 0, h->stream, u->u, u->u32,
+                               uint64_t(2 * u->elems()));
+            QS_HIP(hipGetLastError());
+            u->u32_valid = true;
+        }
+        ua = u->u32;
+    }
+    if (!use_blas()) {
+        // every column with the control bit set: batch b (of the bits above
+        // ctrl) and run r (of the bits between m and ctrl) start at
+        // 2^ctrl + b 2^(ctrl+1) + r 2^m
+        ColMap cols;
+        cols.base = uint64_t(1) << ctrl;
+        cols.ld = uint64_t(1) << m;
+        cols.runs_log = ctrl - m;
+        cols.stride_log = ctrl + 1;
+        const uint64_t half = h->dim() / 2;
+        if ((rc = launch_cgemm(h->stream, h->dtype, false, ua, int64_t(1) << m, 1 << m, 1 << m, h->psi, cols,
+                               h->scratch, cols, h->dim() >> (m + 1))))
+            return rc;
+        if (h->dtype == QS_C128)
+            hipLaunchKernelGGL(k_copy_ctrl0<double2>, dim3(grid_of(half)), dim3(256), 0, h->stream,
+                               static_cast<const double2 *>(h->psi), static_cast<double2 *>(h->scratch), ctrl, half);
+        else
+            hipLaunchKernelGGL(k_copy_ctrl0<float2>, dim3(grid_of(half)), dim3(256), 0, h->stream,
+                               static_cast<const float2 *>(h->psi), static_cast<float2 *>(h->scratch), ctrl, half);
+        QS_HIP(hipGetLastError());
+        if (h->borrowed) {
+            QS_HIP(hipMemcpyAsync(h->psi, h->scratch, h->dim() * h->amp_bytes(), hipMemcpyDeviceToDevice,
+                                  h->stream));
+        } else {
+            std::swap(h->psi, h->scratch);
+        }
+        return QS_OK;
+    }
     rocblas_handle b = blas(rc);
     if (rc) return rc;
-    if ((rc = ensure_scratch(h))) return rc;
-    // the BLAS library runs on the handle's stream; the unitary must be ready there
-    if (u->stream != h->stream) QS_HIP(hipStreamSynchronize(u->stream));
     if ((rc = blas_check(rocblas_set_stream(b, h->stream), "rocblas_set_stream"))) return rc;
     const rocblas_int d = rocblas_int(1) << m;
     const rocblas_int runs = rocblas_int(1) << (ctrl - m);                 // columns per batch
@@ -350,13 +438,6 @@ int qs_apply_controlled_unitary(qs_handle h, qs_unitary u, int ctrl)
         hipLaunchKernelGGL(k_copy_ctrl0<double2>, dim3(grid_of(half)), dim3(256), 0, h->stream,
                            static_cast<const double2 *>(h->psi), static_cast<double2 *>(h->scratch), ctrl, half);
     } else {
-        if (!u->u32) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->u32), u->elems() * 8));
-        if (!u->u32_valid) {
-            hipLaunchKernelGGL(k_cast_u, dim3(grid_of(2 * u->elems())), dim3(256), 0, h->stream, u->u, u->u32,
-                               uint64_t(2 * u->elems()));
-            QS_HIP(hipGetLastError());
-            u->u32_valid = true;
-        }
         const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
         const auto *A = reinterpret_cast<const rocblas_float_complex *>(u->u32);
         const auto *B = reinterpret_cast<const rocblas_float_complex *>(h->psi) + first;
@@ -405,9 +486,13 @@ int qs_unitary_eig(qs_unitary u)
     if (!u->theta) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->theta), d * sizeof(double)));
     if (!u->tmp) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->tmp), bytes));
     double2 *D = nullptr, *Q = nullptr;
-    double *lam = nullptr, *work = nullptr;
+    double *lam = nullptr, *work = nullptr, *part = nullptr;
     rocblas_int *info = nullptr;
+    u->eig_valid = false;
+    u->eig_offdiag = -1.0;
+    constexpr unsigned kOffBlocks = 1024;
     auto cleanup = [&](int r) {
+        if (part) (void)hipFree(part);
         if (D) (void)hipFree(D);
         if (Q) (void)hipFree(Q);
         if (lam) (void)hipFree(lam);
@@ -420,7 +505,8 @@ int qs_unitary_eig(qs_unitary u)
         (e = hipMalloc(reinterpret_cast<void **>(&Q), (d / 2 + 1) * 4 * sizeof(double2))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&lam), d * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void **>(&work), d * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void **>(&info), sizeof(rocblas_int))) != hipSuccess)
+        (e = hipMalloc(reinterpret_cast<void **>(&info), sizeof(rocblas_int))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&part), kOffBlocks * sizeof(double))) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc(eigendecomposition)"));
     if ((rc = blas_check(rocblas_set_stream(bl, u->stream), "rocblas_set_stream"))) return cleanup(rc);
     const double beta = 0.4011269376164746;   // tan(0.38196...): mirror axis of no special phase
@@ -438,7 +524,16 @@ int qs_unitary_eig(qs_unitary u)
     auto *Vd = reinterpret_cast<rocblas_double_complex *>(V);
     auto *W = reinterpret_cast<rocblas_double_complex *>(u->tmp);
     auto *Dd = reinterpret_cast<rocblas_double_complex *>(D);
+    const bool lib = use_blas();
     auto form_d = [&]() {   // D = V^dagger (U V)
+        if (!lib) {
+            int r = launch_cgemm(u->stream, QS_C128, false, Ud, n, n, n, Vd, plain_cols(uint64_t(n)), W,
+                                 plain_cols(uint64_t(n)), uint64_t(n));
+            if (!r)
+                r = launch_cgemm(u->stream, QS_C128, true, Vd, n, n, n, W, plain_cols(uint64_t(n)), Dd,
+                                 plain_cols(uint64_t(n)), uint64_t(n));
+            return r;
+        }
         int r = blas_check(rocblas_zgemm(bl, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, Ud, n,
                                          Vd, n, &zero, W, n),
                            "rocblas_zgemm");
@@ -459,15 +554,41 @@ int qs_unitary_eig(qs_unitary u)
         if ((rc = form_d())) return cleanup(rc);
     }
     hipLaunchKernelGGL(k_diag_arg, dim3(grid_of(d)), dim3(256), 0, u->stream, D, u->theta, u->m);
+    // residual: V^dagger U V must be diagonal. A cluster of three or more
+    // eigenphases that the blend maps to one eigenvalue (mirror images about
+    // atan(beta), with a multiplicity) is not separated by the pair passes
+    // and shows up here.
+    const unsigned nb = unsigned(std::min<uint64_t>(kOffBlocks, (u->elems() + 255) / 256));
+    hipLaunchKernelGGL(k_offdiag_max, dim3(nb), dim3(256), 0, u->stream, D, u->m, part);
+    std::vector<double> hpart(nb);
     rocblas_int hinfo = 0;
     if ((e = hipGetLastError()) != hipSuccess ||
         (e = hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, u->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(hpart.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, u->stream)) !=
+            hipSuccess ||
         (e = hipStreamSynchronize(u->stream)) != hipSuccess)
         return cleanup(hip_fail(e, "eigendecomposition"));
     if (hinfo != 0) return cleanup(fail(QS_EDEVICE, "rocsolver_zheevd did not converge (info %d)", int(hinfo)));
+    double off = 0.0;
+    for (double v : hpart) off = std::max(off, v);
+    u->eig_offdiag = off;
+    if (!(off <= kEigResidualTol))
+        return cleanup(fail(QS_EUNSUPPORTED,
+                            "eigenvectors not resolved: max off-diagonal of V^dagger U V is %.3e (> %.0e); "
+                            "a cluster of mirror-image eigenphases with a multiplicity; use the squaring route",
+                            off, kEigResidualTol));
     u->eig_valid = true;
     u->v32_valid = false;
     return cleanup(QS_OK);
+}
+
+int qs_unitary_eig_residual(qs_unitary u, double *offdiag)
+{
+    clear_error();
+    if (!u || !offdiag) return fail(QS_EINVAL, "NULL argument");
+    if (u->eig_offdiag < 0) return fail(QS_EINVAL, "no eigendecomposition attempted");
+    *offdiag = u->eig_offdiag;
+    return QS_OK;
 }
 
 int qs_unitary_eig_get(qs_unitary u, double *host_theta, double *host_v)
@@ -497,15 +618,42 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b)
     if (b < 1 || b > 62 || ctrl_lo < m || ctrl_lo + b > h->n)
         return fail(QS_EINVAL, "control register [%d, %d) must lie in [%d, %d)", ctrl_lo, ctrl_lo + b, m, h->n);
     int rc = QS_OK;
-    rocblas_handle bl = blas(rc);
-    if (rc) return rc;
     if ((rc = ensure_scratch(h))) return rc;
     if (u->stream != h->stream) QS_HIP(hipStreamSynchronize(u->stream));
+    if (h->dtype == QS_C64) {
+        if (!u->v32) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->v32), u->elems() * 8));
+        if (!u->v32_valid) {
+            hipLaunchKernelGGL(k_cast_u, dim3(grid_of(2 * u->elems())), dim3(256), 0, h->stream, u->v, u->v32,
+                               uint64_t(2 * u->elems()));
+            QS_HIP(hipGetLastError());
+            u->v32_valid = true;
+        }
+    }
+    const uint64_t ncols = h->dim() >> m;
+    const int cshift = ctrl_lo - m;
+    if (!use_blas()) {
+        // Y = V^dagger X, Y *= e^(i c theta), X = V Y over the state as a
+        // 2^m x 2^(n-m) column-major matrix
+        const int dd = 1 << m;
+        const void *V = h->dtype == QS_C128 ? static_cast<const void *>(u->v) : static_cast<const void *>(u->v32);
+        if ((rc = launch_cgemm(h->stream, h->dtype, true, V, dd, dd, dd, h->psi, plain_cols(uint64_t(dd)), h->scratch,
+                               plain_cols(uint64_t(dd)), ncols)))
+            return rc;
+        if (h->dtype == QS_C128)
+            hipLaunchKernelGGL((k_eig_phase<double2, double>), dim3(grid_of(h->dim())), dim3(256), 0, h->stream,
+                               static_cast<double2 *>(h->scratch), u->theta, m, cshift, b, uint64_t(0), h->dim());
+        else
+            hipLaunchKernelGGL((k_eig_phase<float2, float>), dim3(grid_of(h->dim())), dim3(256), 0, h->stream,
+                               static_cast<float2 *>(h->scratch), u->theta, m, cshift, b, uint64_t(0), h->dim());
+        QS_HIP(hipGetLastError());
+        return launch_cgemm(h->stream, h->dtype, false, V, dd, dd, dd, h->scratch, plain_cols(uint64_t(dd)), h->psi,
+                            plain_cols(uint64_t(dd)), ncols);
+    }
+    rocblas_handle bl = blas(rc);
+    if (rc) return rc;
     if ((rc = blas_check(rocblas_set_stream(bl, h->stream), "rocblas_set_stream"))) return rc;
     const rocblas_int d = rocblas_int(1) << m;
-    const uint64_t ncols = h->dim() >> m;
     const uint64_t chunk = std::min<uint64_t>(ncols, 1ull << 30);      // 32-bit BLAS sizes
-    const int cshift = ctrl_lo - m;
     if (h->dtype == QS_C128) {
         const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
         const auto *V = reinterpret_cast<const rocblas_double_complex *>(u->v);
@@ -527,13 +675,6 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b)
                 return rc;
         }
     } else {
-        if (!u->v32) QS_HIP(hipMalloc(reinterpret_cast<void **>(&u->v32), u->elems() * 8));
-        if (!u->v32_valid) {
-            hipLaunchKernelGGL(k_cast_u, dim3(grid_of(2 * u->elems())), dim3(256), 0, h->stream, u->v, u->v32,
-                               uint64_t(2 * u->elems()));
-            QS_HIP(hipGetLastError());
-            u->v32_valid = true;
-        }
         const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
         const auto *V = reinterpret_cast<const rocblas_float_complex *>(u->v32);
         for (uint64_t c0 = 0; c0 < ncols; c0 += chunk) {
@@ -552,6 +693,26 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b)
                                                Y, d, &zero, X, d),
                                  "rocblas_cgemm")))
                 return rc;
+        }
+    }
+    return QS_OK;
+}
+
+int qs_qpe_crossover_bits(double t_apply, double t_build, double t_op, int per_bit, int bmax, int *out_bits)
+{
+    clear_error();
+    if (!out_bits) return fail(QS_EINVAL, "NULL output");
+    *out_bits = 0;
+    if (!(std::isfinite(t_apply) && std::isfinite(t_build) && std::isfinite(t_op)) || t_apply < 0 ||
+        t_build < 0 || t_op < 0)
+        return fail(QS_EINVAL, "times must be finite and non-negative");
+    if (bmax < 1 || bmax > 1000) return fail(QS_EINVAL, "bmax=%d outside [1, 1000]", bmax);
+    for (int b = 1; b <= bmax; ++b) {
+        const double emulate = t_build + (per_bit ? double(b) * t_op : t_op);
+        const double simulate = (std::ldexp(1.0, b) - 1.0) * t_apply;
+        if (simulate >= emulate) {
+            *out_bits = b;
+            return QS_OK;
         }
     }
     return QS_OK;

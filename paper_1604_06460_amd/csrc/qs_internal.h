@@ -107,6 +107,10 @@ void classify(const double *m, int k, GateDesc &d);
 int launch_dense(qs_state *h, const GateDesc &d, const void *dmat);
 int launch_diag(qs_state *h, const GateDesc &d, const void *dmat, int stride /*row stride in entries*/);
 int launch_phase1(qs_state *h, const GateDesc &d, const void *dmat);
+// Diagonal block with its diagonal also on the host (hdiag: 2^k complex
+// FP64 entries): sweeps only the target patterns whose entry is not one.
+int launch_diag_block(qs_state *h, const GateDesc &d, const void *dmat, int row_stride, const double *hdiag);
+double diag_changed_fraction(const double *hdiag, int k);
 int launch_monomial(qs_state *h, const GateDesc &d, const void *dmat);
 int launch_cast_f64_to_f32(hipStream_t s, const double *src, float *dst, size_t count);
 // FP32 MFMA path for dense 6-qubit blocks on complex64 states (mfma.hip)
@@ -134,6 +138,19 @@ struct ComposeBlock {
 int launch_compose(hipStream_t s, int n_blocks, const ComposeBlock *dblocks,
                    const ComposeGate *dgates, const double *dmats, double *dout,
                    int max_k);
+
+// Complex GEMM on the matrix cores (cgemm.hip): C = op(A) B, column-major,
+// op(A) = A or A^dagger (conj_a), A is M x K with leading dimension lda. B
+// and C are given as column lists: column c starts at
+// base + ((c >> runs_log) << stride_log) + (c & (2^runs_log - 1)) * ld
+// elements, so a strided batch of runs-column blocks is one product. dtype
+// QS_C128 runs on FP64 matrix cores, QS_C64 on FP32 ones.
+struct ColMap {
+    uint64_t base = 0, ld = 0;
+    int runs_log = 62, stride_log = 0;
+};
+int launch_cgemm(hipStream_t s, int dtype, bool conj_a, const void *A, int64_t lda, int M, int K, const void *B,
+                 ColMap bm, void *C, ColMap cm, uint64_t ncols);
 
 // Planner (host only)
 struct Plan {
@@ -177,6 +194,8 @@ struct qs_program_t {
     std::vector<int> k;                  // per block
     std::vector<std::vector<int>> qubits;
     std::vector<int> diagonal;           // 1 if the block is diagonal
+    std::vector<std::vector<double>> hdiag;  // diagonal blocks: their 2^k FP64 entries (host)
+    std::vector<double> changed;         // fraction of amplitudes a block changes (1 for dense)
     std::vector<int64_t> mat_off;        // offset in doubles into dmats
     double *dmats = nullptr;             // FP64 composed matrices (device)
     float *dmats32 = nullptr;            // FP32 copies (device)

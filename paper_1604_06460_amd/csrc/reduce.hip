@@ -119,20 +119,32 @@ __device__ __forceinline__ uint32_t outcome_of(uint64_t i, const QArgs &qa)
 }
 
 // Marginals, small m: per-workgroup histogram in LDS, one row of partials
-// per workgroup.
+// per workgroup. A wave covers 64 consecutive, 64-aligned indices, so when
+// every measured qubit is 6 or above (wave_uniform) all its lanes fall in
+// one bin: the wave sums its 64 probabilities first and adds them with one
+// LDS atomic, instead of 64 atomics on one address that the LDS serialises.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_hist_lds(const typename V2<R>::T *__restrict__ psi,
-                                                       uint64_t dim, QArgs qa,
+                                                       uint64_t dim, QArgs qa, int wave_uniform,
                                                        double *__restrict__ partial)
 {
     extern __shared__ double hist[];
     const int M = 1 << qa.m;
     for (int o = threadIdx.x; o < M; o += kThreads) hist[o] = 0.0;
     __syncthreads();
-    for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < dim;
-         i += uint64_t(gridDim.x) * kThreads) {
-        const double x = double(psi[i].x), y = double(psi[i].y);
-        atomicAdd(&hist[outcome_of(i, qa)], fma(x, x, y * y));
+    if (wave_uniform) {
+        for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < dim;
+             i += uint64_t(gridDim.x) * kThreads) {
+            const double x = double(psi[i].x), y = double(psi[i].y);
+            const double s = wave_sum(fma(x, x, y * y));
+            if ((threadIdx.x & 63) == 0) atomicAdd(&hist[outcome_of(i, qa)], s);
+        }
+    } else {
+        for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < dim;
+             i += uint64_t(gridDim.x) * kThreads) {
+            const double x = double(psi[i].x), y = double(psi[i].y);
+            atomicAdd(&hist[outcome_of(i, qa)], fma(x, x, y * y));
+        }
     }
     __syncthreads();
     for (int o = threadIdx.x; o < M; o += kThreads) partial[size_t(blockIdx.x) * M + o] = hist[o];
@@ -365,12 +377,17 @@ int measure(qs_state *h, int m, const int *qubits, int shots, const double *u, u
     double *du = reinterpret_cast<double *>(dout + shots);
     if (lds_path) {
         const size_t lds = sizeof(double) * size_t(M);
+        int lowest = 64;
+        for (int r = 0; r < m; ++r) lowest = std::min(lowest, qubits[r]);
+        // wave-uniform bins need 64-aligned waves: the grid stride is a
+        // multiple of 256, and a state below 64 amplitudes has one partial wave
+        const int uniform = (lowest >= 6 && h->dim() >= 64) ? 1 : 0;
         if (h->dtype == QS_C128)
             hipLaunchKernelGGL(k_hist_lds<double>, dim3(g), dim3(kThreads), lds, h->stream,
-                               static_cast<const double2 *>(h->psi), h->dim(), qa, part);
+                               static_cast<const double2 *>(h->psi), h->dim(), qa, uniform, part);
         else
             hipLaunchKernelGGL(k_hist_lds<float>, dim3(g), dim3(kThreads), lds, h->stream,
-                               static_cast<const float2 *>(h->psi), h->dim(), qa, part);
+                               static_cast<const float2 *>(h->psi), h->dim(), qa, uniform, part);
         QS_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_hist_cols, dim3((M + kThreads - 1) / kThreads), dim3(kThreads), 0,
                            h->stream, part, int(rows), M, p);

@@ -767,6 +767,43 @@ int diag_k(qs_state *h, const GateDesc &d, const void *dmat, int row_stride)
     return QS_OK;
 }
 
+// The same kernel restricted to the amplitudes whose high target bits (and
+// controls) equal one pinned pattern: those bits join the fixed positions,
+// so a launch touches 2^-npin of the state. Targets inside a 128-byte line
+// stay free and pick their entry from the table, so whole lines are read
+// and written.
+template <typename R, typename IT, int K>
+int diag_pinned_k(qs_state *h, const GateDesc &d, const void *dmat, int row_stride, const int *pin,
+                  int npin, uint64_t pin_vals)
+{
+    using C2 = typename V2<R>::T;
+    FixArgs fx;
+    if (int rc = make_fix(pin, npin, pin_vals, fx)) return rc;
+    OffArgs<K> tg;
+    for (int m = 0; m < K; ++m) tg.o[m] = uint64_t(d.targets[m]);
+    const IT n_items = IT(h->dim() >> npin);
+    hipLaunchKernelGGL((k_diag<R, K, IT>), dim3(grid_for(n_items)), dim3(kBlock), 0, h->stream,
+                       static_cast<C2 *>(h->psi), static_cast<const R *>(dmat), row_stride,
+                       n_items, fx, tg);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+template <typename R, typename IT>
+int diag_pinned_dispatch(qs_state *h, const GateDesc &d, const void *dmat, int row_stride, const int *pin,
+                         int npin, uint64_t pin_vals)
+{
+    switch (d.k) {
+    case 1: return diag_pinned_k<R, IT, 1>(h, d, dmat, row_stride, pin, npin, pin_vals);
+    case 2: return diag_pinned_k<R, IT, 2>(h, d, dmat, row_stride, pin, npin, pin_vals);
+    case 3: return diag_pinned_k<R, IT, 3>(h, d, dmat, row_stride, pin, npin, pin_vals);
+    case 4: return diag_pinned_k<R, IT, 4>(h, d, dmat, row_stride, pin, npin, pin_vals);
+    case 5: return diag_pinned_k<R, IT, 5>(h, d, dmat, row_stride, pin, npin, pin_vals);
+    case 6: return diag_pinned_k<R, IT, 6>(h, d, dmat, row_stride, pin, npin, pin_vals);
+    default: return fail(QS_EUNSUPPORTED, "diagonal gate width %d", d.k);
+    }
+}
+
 template <typename R, typename IT>
 int diag_dispatch(qs_state *h, const GateDesc &d, const void *dmat, int row_stride)
 {
@@ -917,6 +954,79 @@ int launch_diag(qs_state *h, const GateDesc &d, const void *dmat, int row_stride
                  : diag_dispatch<float, uint64_t>(h, d, dmat, row_stride);
 }
 
+// Fraction of the state a diagonal block must change: the local indices
+// whose entry is not exactly one, over 2^k.
+double diag_changed_fraction(const double *hdiag, int k)
+{
+    int cnt = 0;
+    for (int j = 0; j < (1 << k); ++j)
+        if (!(hdiag[2 * j] == 1.0 && hdiag[2 * j + 1] == 0.0)) ++cnt;
+    return double(cnt) / double(1 << k);
+}
+
+// A diagonal block whose entries are known on the host (hdiag: 2^k complex
+// FP64 values, the block matrix's diagonal). A conditional phase shift moves
+// only the amplitudes that carry its phase (Sec. III-B); a product of them
+// (CZ layers, controlled phases fused into one block) is treated the same
+// way: only the patterns of the targets whose entry differs from one are
+// swept. With all entries one nothing is launched; with one entry the phase
+// kernel runs; otherwise every distinct pattern of the targets above the
+// 128-byte line (those inside a line pick their entry per amplitude, so
+// whole lines are rewritten) gets one pinned launch, unless the pinned
+// launches together would touch more than half the state, in which case one
+// elementwise pass over the state is cheaper.
+int launch_phase1_host(qs_state *h, const GateDesc &d, double pr, double pi);
+
+int launch_diag_block(qs_state *h, const GateDesc &din, const void *dmat, int row_stride, const double *hdiag)
+{
+    const int K = din.k, D = 1 << K;
+    std::vector<int> changed;
+    for (int j = 0; j < D; ++j)
+        if (!(hdiag[2 * j] == 1.0 && hdiag[2 * j + 1] == 0.0)) changed.push_back(j);
+    if (changed.empty()) return QS_OK;
+    if (changed.size() == 1) {
+        GateDesc d = din;
+        d.cls = GC_PHASE1;
+        d.phase_index = changed[0];
+        const size_t j = size_t(changed[0]);
+        return launch_phase1_host(h, d, hdiag[2 * j], hdiag[2 * j + 1]);
+    }
+    const int line_bits = h->amp_bytes() == 16 ? 3 : 4;
+    int hi_bit[QS_MAX_K], nhi = 0;
+    uint32_t hi_mask = 0;
+    for (int m = 0; m < K; ++m)
+        if (din.targets[m] >= line_bits) {
+            hi_bit[nhi++] = m;
+            hi_mask |= 1u << m;
+        }
+    std::vector<uint32_t> pats;
+    for (int j : changed) pats.push_back(uint32_t(j) & hi_mask);
+    std::sort(pats.begin(), pats.end());
+    pats.erase(std::unique(pats.begin(), pats.end()), pats.end());
+    GateDesc d = din;
+    d.cls = GC_DIAG;
+    if (2 * pats.size() > (size_t(1) << nhi)) return launch_diag(h, d, dmat, row_stride);
+    int pin[64], npin = 0;
+    for (int i = 0; i < nhi; ++i) pin[npin++] = din.targets[hi_bit[i]];
+    for (int q = 0; q < 64; ++q)
+        if ((din.ctrl_mask >> q) & 1) pin[npin++] = q;
+    const bool small = h->n <= 31;
+    for (uint32_t pt : pats) {
+        uint64_t vals = din.ctrl_vals;
+        for (int i = 0; i < nhi; ++i)
+            if ((pt >> hi_bit[i]) & 1) vals |= 1ull << din.targets[hi_bit[i]];
+        int rc;
+        if (h->dtype == QS_C128)
+            rc = small ? diag_pinned_dispatch<double, uint32_t>(h, d, dmat, row_stride, pin, npin, vals)
+                       : diag_pinned_dispatch<double, uint64_t>(h, d, dmat, row_stride, pin, npin, vals);
+        else
+            rc = small ? diag_pinned_dispatch<float, uint32_t>(h, d, dmat, row_stride, pin, npin, vals)
+                       : diag_pinned_dispatch<float, uint64_t>(h, d, dmat, row_stride, pin, npin, vals);
+        if (rc) return rc;
+    }
+    return QS_OK;
+}
+
 int launch_monomial_host(qs_state *h, const GateDesc &d, const double *hmat)
 {
     const bool small = h->n <= 31;
@@ -985,7 +1095,14 @@ int enqueue_gate(qs_state *h, const GateDesc &din, const double *hmat)
             return rc;
         dm = d32;
     }
-    if (d.cls == GC_DIAG) return launch_diag(h, d, dm, int(D));
+    if (d.cls == GC_DIAG) {
+        std::vector<double> hdiag(2 * D);
+        for (size_t j = 0; j < D; ++j) {
+            hdiag[2 * j] = hmat[2 * (j * D + j)];
+            hdiag[2 * j + 1] = hmat[2 * (j * D + j) + 1];
+        }
+        return launch_diag_block(h, d, dm, int(D), hdiag.data());
+    }
     return launch_dense(h, d, dm);
 }
 

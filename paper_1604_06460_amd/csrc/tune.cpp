@@ -35,6 +35,7 @@ Range range_of(int p)
     case QS_TUNE_FFT_KERNEL: return {1, 2};
     case QS_TUNE_SWEEP_NT: return {1, 3};
     case QS_TUNE_FFT_NT: return {1, 3};
+    case QS_TUNE_GEMM_LIB: return {1, 1};
     default: return {0, -1};
     }
 }

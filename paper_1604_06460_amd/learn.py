@@ -79,6 +79,11 @@ def fit(X, T, mask, epochs=80, batch=256, lr=2e-3, seed=0):
     inv = np.where(std > 1e-4 * np.maximum(1.0, np.abs(mean)), 1.0 / np.maximum(std, 1e-30), 0.0)
     m = Q.Mlp(seed=seed)
     m.set_norm(mean, inv)
+    # training range per feature: the learned policy falls back to the
+    # heuristic for segments outside it; switched-off features are not checked
+    lo = np.where(inv > 0, X64.min(0), -3.0e38)
+    hi = np.where(inv > 0, X64.max(0), 3.0e38)
+    m.set_range(lo, hi)
     loss = m.train(X, T, mask, epochs, batch, lr, seed)
     return m, loss
 

@@ -31,6 +31,7 @@ QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED, QS_ENOTUNITARY = range
 QS_MAX_K = 6
 QS_PERM_MODMUL, QS_PERM_TABLE = 0, 1
 QS_ARITH_MUL, QS_ARITH_DIV = 0, 1
+QS_BLOCK_DENSE, QS_BLOCK_DIAGONAL, QS_BLOCK_IDENTITY = 0, 1, 2
 
 _P = C.c_void_p
 _I = C.c_int
@@ -87,6 +88,12 @@ _sig("qs_compile", [_P, C.POINTER(Circuit), _I, C.POINTER(_P)])
 _sig("qs_program_info", [_P, C.POINTER(_I), _P, C.POINTER(_D)])
 _sig("qs_program_block", [_P, _I, _P, _P])
 _sig("qs_run_program", [_P, _P])
+_sig("qs_run_program_range", [_P, _P, _I, _I])
+_sig("qs_qpe_crossover_bits", [_D, _D, _D, _I, _I, C.POINTER(_I)])
+_sig("qs_unitary_eig_residual", [_P, C.POINTER(_D)])
+_sig("qs_mlp_set_range", [_P, _P, _P])
+_sig("qs_mlp_choose_stats", [_P, _P])
+_sig("qs_program_block_kind", [_P, _I, C.POINTER(_I), C.POINTER(_D)])
 _sig("qs_program_free", [_P])
 _sig("qs_apply_circuit", [_P, C.POINTER(Circuit), _I])
 _sig("qs_emulate_qft", [_P, _I, _I, _I])
@@ -140,6 +147,23 @@ class Mlp:
         m = np.ascontiguousarray(mean, dtype=np.float32)
         s = np.ascontiguousarray(inv_std, dtype=np.float32)
         _chk(_L.qs_mlp_set_norm(self._h, _ptr(m), _ptr(s)))
+
+    def set_range(self, lo, hi):
+        """Training range of the raw features (None, None: no range check)."""
+        if lo is None and hi is None:
+            _chk(_L.qs_mlp_set_range(self._h, None, None))
+            return
+        a = np.ascontiguousarray(lo, dtype=np.float32)
+        b = np.ascontiguousarray(hi, dtype=np.float32)
+        _chk(_L.qs_mlp_set_range(self._h, _ptr(a), _ptr(b)))
+
+    def choose_stats(self):
+        """Segments of the last learned choice: learned, out of range,
+        non-finite prediction, gain below the margin."""
+        out = np.zeros(4, dtype=np.int32)
+        _chk(_L.qs_mlp_choose_stats(self._h, _ptr(out)))
+        return dict(zip(("learned", "fallback_range", "fallback_nonfinite", "fallback_margin"),
+                        (int(v) for v in out)))
 
     def forward(self, x):
         x = np.ascontiguousarray(x, dtype=np.float32)
@@ -259,6 +283,12 @@ class Program:
         _chk(_L.qs_program_info(self._h, None, _ptr(ks), None))
         return nb.value, ks[:nb.value].copy(), by.value
 
+    def block_kind(self, b):
+        """(QS_BLOCK_* kind, fraction of amplitudes block b changes)."""
+        kind, frac = _I(0), _D(0)
+        _chk(_L.qs_program_block_kind(self._h, int(b), C.byref(kind), C.byref(frac)))
+        return kind.value, frac.value
+
     def block(self, b):
         nb, ks, _ = self.info()
         k = int(ks[b])
@@ -367,6 +397,9 @@ class State:
 
     def run(self, program):
         _chk(_L.qs_run_program(self._h, program.handle))
+
+    def run_range(self, program, b0, b1):
+        _chk(_L.qs_run_program_range(self._h, program.handle, int(b0), int(b1)))
 
     def apply_circuit(self, gates, max_k):
         pc = PackedCircuit(gates)
@@ -522,13 +555,13 @@ _sig("qs_tune_classify", [_I, _I, _I, _P, C.POINTER(_I), C.POINTER(_I)])
 
 (QS_TUNE_SWEEP_PATH, QS_TUNE_SWEEP_WG_PER_CU, QS_TUNE_FFT_DIGIT, QS_TUNE_FFT_LDS_KB,
  QS_TUNE_MFMA_WG_PER_CU, QS_TUNE_BATCH_GANG_SHARE, QS_TUNE_BATCH_BARRIER_AMPS, QS_TUNE_FFT_KERNEL,
- QS_TUNE_SWEEP_NT, QS_TUNE_FFT_NT) = range(10)
+ QS_TUNE_SWEEP_NT, QS_TUNE_FFT_NT, QS_TUNE_GEMM_LIB) = range(11)
 QS_TCLS_SUBLINE, QS_TCLS_SUBWAVE, QS_TCLS_HIGH = range(3)
 TUNE_PARAMS = {"sweep_path": QS_TUNE_SWEEP_PATH, "sweep_wg_per_cu": QS_TUNE_SWEEP_WG_PER_CU,
                "fft_digit": QS_TUNE_FFT_DIGIT, "fft_lds_kb": QS_TUNE_FFT_LDS_KB,
                "mfma_wg_per_cu": QS_TUNE_MFMA_WG_PER_CU, "batch_gang_share": QS_TUNE_BATCH_GANG_SHARE,
                "batch_barrier_amps": QS_TUNE_BATCH_BARRIER_AMPS, "fft_kernel": QS_TUNE_FFT_KERNEL,
-               "sweep_nt": QS_TUNE_SWEEP_NT, "fft_nt": QS_TUNE_FFT_NT}
+               "sweep_nt": QS_TUNE_SWEEP_NT, "fft_nt": QS_TUNE_FFT_NT, "gemm_lib": QS_TUNE_GEMM_LIB}
 TUNED_FILE = os.path.join(_HERE, "tuned", "gfx950.json")
 
 
@@ -610,6 +643,12 @@ class Unitary:
         """Eigendecomposition U = V diag(e^(i theta)) V^dagger on the device."""
         _chk(_L.qs_unitary_eig(self._h))
 
+    def eig_residual(self):
+        """Max off-diagonal magnitude of V^dagger U V from the last eig()."""
+        out = _D(0)
+        _chk(_L.qs_unitary_eig_residual(self._h, C.byref(out)))
+        return out.value
+
     def eig_get(self):
         """(theta, V): eigenphases and eigenvectors (columns) on the host."""
         d = 1 << self.m
@@ -641,12 +680,8 @@ def emulate_qpe_powers(state, gates, m, ctrl_lo, b, max_k=4):
 
 
 def qpe_crossover_bits(t_apply, t_build, t_op, per_bit=True, bmax=200):
-    """Precision (bits) from which emulated phase estimation is no slower than
-    simulation (Sec. III-C, the rule behind Table 2): the simulator applies U
-    2^b - 1 times; the emulator builds U once and then pays t_op per bit
-    (a squaring) or once (an eigendecomposition)."""
-    for b in range(1, bmax + 1):
-        emu = t_build + (b * t_op if per_bit else t_op)
-        if (2 ** b - 1) * t_apply >= emu:
-            return b
-    return None
+    """qs_qpe_crossover_bits (Table 2's rule); None if no b <= bmax."""
+    out = _I(0)
+    _chk(_L.qs_qpe_crossover_bits(float(t_apply), float(t_build), float(t_op), int(bool(per_bit)),
+                                  int(bmax), C.byref(out)))
+    return out.value or None

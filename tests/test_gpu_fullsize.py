@@ -63,7 +63,14 @@ def test_30q_bench_circuit_then_inverse_returns_to_zero(Q, S):
     for gl in (gates, inv):
         prog = st.compile(gl, 4)
         nb, ks, moves = prog.info()
-        assert nb > 100 and max(ks) <= 4 and moves == nb * 2.0 * 2 ** N
+        kinds = [prog.block_kind(b) for b in range(nb)]
+        assert nb > 100 and max(ks) <= 4
+        # dense blocks move the whole state, diagonal (CZ-only) blocks only
+        # the amplitudes whose sign flips
+        assert moves == sum(f for _, f in kinds) * 2.0 * 2 ** N <= nb * 2.0 * 2 ** N
+        if gl is gates:       # the last layer's CZs form diagonal blocks
+            assert moves < nb * 2.0 * 2 ** N
+        assert all(f == 1.0 for k, f in kinds if k == Q.QS_BLOCK_DENSE)
         st.run(prog)
         prog.free()
     a = st.amplitudes(_sample(N, 64, 9))

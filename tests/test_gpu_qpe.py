@@ -36,6 +36,50 @@ def test_dense_unitary_and_square_vs_oracle(Q, O, S, m, max_k):
     u.free()
 
 
+@pytest.mark.parametrize("m", [8, 9, 10])
+def test_matrix_core_square_vs_oracle_product(Q, O, S, m):
+    """U^2 from the library's matrix-core complex GEMM (several 128 x 128
+    tiles, and one partial tile at m = 8) against the oracle's dense U
+    multiplied by itself in FP64, and against the rocBLAS baseline."""
+    gates = S.tfim_trotter_step(m, dt=0.37)
+    U = O.block_matrix(m, gates)
+    u = Q.Unitary(gates, m)
+    u.square()
+    got = u.get()
+    ref = U @ U
+    assert np.abs(got - ref).max() < 1e-14 * (1 << m)
+    Q.tune_set(Q.QS_TUNE_GEMM_LIB, 1)
+    try:
+        v = Q.Unitary(gates, m)
+        v.square()
+        lib = v.get()
+        v.free()
+    finally:
+        Q.tune_set(Q.QS_TUNE_GEMM_LIB, 0)
+    assert np.abs(got - lib).max() < 1e-14 * (1 << m)
+    u.free()
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_controlled_unitary_many_batches_matrix_core(Q, O, S, dtype):
+    """m = 7 controlled by qubits 7, 9 and 12 of a 14-qubit state: the
+    column lists of the matrix-core GEMM (runs of 2^(c-m) columns in
+    2^(n-c-1) batches) against the oracle's controlled gate list."""
+    m, n = 7, 14
+    gates = S.tfim_trotter_step(m, dt=0.21)
+    u = Q.Unitary(gates, m)
+    psi0 = S.normal_state(n, 44)
+    for ctrl in (7, 9, 12):
+        st = Q.State(n, dtype)
+        st.set(psi0)
+        u.apply_controlled(st, ctrl)
+        ref = O.apply_circuit(psi0, [S.Gate(g.targets, g.matrix, g.ctrl_mask | (1 << ctrl),
+                                            g.ctrl_vals | (1 << ctrl)) for g in gates])
+        assert np.abs(st.get() - ref).max() < TOL[dtype], ctrl
+        st.free()
+    u.free()
+
+
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_controlled_unitary_every_control_position(Q, O, S, dtype):
     m, n = 3, 11
@@ -112,6 +156,54 @@ def test_eig_reconstructs_the_unitary(Q, O, S, m):
     u = Q.Unitary(gates, m)
     u.eig()
     _check_eig(u, U)
+    u.free()
+
+
+@pytest.mark.parametrize("m", [8, 10, 12])
+def test_eig_residual_of_the_ising_step(Q, O, S, m):
+    """The checked residual of the Table 2 example: V^dagger U V is diagonal
+    to within the 1e-10 the entry point demands."""
+    u = Q.Unitary(S.tfim_trotter_step(m), m)
+    u.eig()
+    r = u.eig_residual()
+    print("m=%d eig residual %.3e" % (m, r))
+    assert 0 <= r <= 1e-10
+    u.free()
+
+
+@pytest.mark.parametrize("mult", [(2, 1), (1, 2), (3, 1), (2, 2)])
+def test_eig_mirror_cluster_with_multiplicity_fails_loudly(Q, O, S, mult):
+    """A phase with a multiplicity plus its mirror image about atan(beta):
+    three or more eigenvectors share one eigenvalue of the Hermitian blend,
+    and neighbouring-pair rotations may not separate them. The entry point
+    must then return QS_EUNSUPPORTED with the residual above the bar; when
+    it returns QS_OK the decomposition must be right."""
+    m, d = 4, 16
+    phi = np.arctan(BETA)
+    rng = np.random.default_rng(40 + 3 * mult[0] + mult[1])
+    t1 = 1.1
+    th = rng.uniform(-np.pi, np.pi, d)
+    th[:mult[0]] = t1
+    th[mult[0]:mult[0] + mult[1]] = 2 * phi - t1
+    q, _ = np.linalg.qr(rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+    M = (q * np.exp(1j * th)) @ q.conj().T
+    gates = [S.Gate(tuple(range(m)), M)]
+    U = O.block_matrix(m, gates)
+    u = Q.Unitary(gates, m)
+    try:
+        u.eig()
+    except Q.QSError as e:
+        assert e.status == Q.QS_EUNSUPPORTED, e
+        r = u.eig_residual()
+        print("mult %s: rejected, residual %.3e" % (mult, r))
+        assert r > 1e-10
+        with pytest.raises(Q.QSError):
+            u.eig_get()                          # nothing kept
+    else:
+        r = u.eig_residual()
+        print("mult %s: resolved, residual %.3e" % (mult, r))
+        assert r <= 1e-10
+        _check_eig(u, U, 1e-9)
     u.free()
 
 
