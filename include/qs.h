@@ -309,6 +309,21 @@ int qs_expectation(qs_handle h, uint64_t x_mask, uint64_t y_mask, uint64_t z_mas
  * sum of p exceeds u * sum(p). probs_or_null receives p (2^m doubles) if
  * not NULL. collapse != 0 (requires shots >= 1) projects the state onto the
  * first shot's outcome and renormalises. */
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): qs_expectation without
+ * any allocation or synchronisation. The result, <P> as (re, im) FP64, is
+ * written to device_out (device memory, 2 doubles, 8-byte aligned) on the
+ * handle's stream; the caller reads it after the stream. The per-block
+ * partial sums live in a library-static device array of 4096 doubles
+ * (32 KiB) per GPU, resolved once per device on the first call and kept
+ * until the process ends; every reduction fits it (at most 2048 blocks of
+ * two partials), a larger request would fail with QS_EUNSUPPORTED. Calls that
+ * overlap on one GPU (two streams, or two threads) race on that array:
+ * serialise them. Arguments are checked as in qs_expectation; QS_EINVAL for
+ * a NULL device_out. */
+int qs_expectation_noalloc(qs_handle h, uint64_t x_mask, uint64_t y_mask, uint64_t z_mask,
+                           double *device_out);
+
 int qs_measure(qs_handle h, int m, const int *qubits, int shots, const double *uniforms,
                uint64_t *outcomes, double *probs_or_null, int collapse);
 

@@ -668,6 +668,17 @@ int qs_expectation(qs_handle h, uint64_t x_mask, uint64_t y_mask, uint64_t z_mas
     return reduce_pauli(h, x_mask, y_mask, z_mask, out_re, out_im);
 }
 
+int qs_expectation_noalloc(qs_handle h, uint64_t x_mask, uint64_t y_mask, uint64_t z_mask, double *device_out)
+{
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!device_out) return fail(QS_EINVAL, "NULL device output");
+    if ((x_mask & y_mask) || (x_mask & z_mask) || (y_mask & z_mask))
+        return fail(QS_EINVAL, "Pauli masks overlap");
+    if (h->n < 64 && ((x_mask | y_mask | z_mask) >> h->n)) return fail(QS_EINVAL, "Pauli mask outside the state");
+    return reduce_pauli_noalloc(h, x_mask, y_mask, z_mask, device_out);
+}
+
 int qs_measure(qs_handle h, int m, const int *qubits, int shots, const double *uniforms,
                uint64_t *outcomes, double *probs_or_null, int collapse)
 {

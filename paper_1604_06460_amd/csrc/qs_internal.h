@@ -169,6 +169,9 @@ inline int far_qubit(size_t amp_bytes) { return amp_bytes == 16 ? 20 : 21; }
 // Reductions (reduce.hip)
 int reduce_norm2(qs_state *h, double *out);
 int reduce_pauli(qs_state *h, uint64_t xm, uint64_t ym, uint64_t zm, double *re, double *im);
+// The same into device memory (out[0] = re, out[1] = im), partial sums in
+// the library's static scratch: no allocation, no synchronisation.
+int reduce_pauli_noalloc(qs_state *h, uint64_t xm, uint64_t ym, uint64_t zm, double *device_out);
 int gather_amplitudes(qs_state *h, int count, const uint64_t *indices, void *host_dst);
 int emulate_qft(qs_state *h, int q_lo, int m, int inverse);
 int measure(qs_state *h, int m, const int *qubits, int shots, const double *u,

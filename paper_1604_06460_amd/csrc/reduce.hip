@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace qs {
 namespace {
@@ -264,6 +265,64 @@ __global__ void k_gather_amps(const typename V2<R>::T *__restrict__ psi,
     if (t < count) out[t] = psi[idx[t]];
 }
 
+// Fixed-order final sum of the Pauli partials (as k_finish), times
+// i^{popcount(y)} (y_pow = popcount(y) mod 4), written to device memory.
+__global__ void k_finish_pauli(const double *__restrict__ partial, int count, int y_pow, double *__restrict__ out)
+{
+    __shared__ double sh[kThreads / 64];
+    double s[2];
+    for (int c = 0; c < 2; ++c) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < count; i += kThreads) v += partial[size_t(i) * 2 + c];
+        s[c] = block_sum(v, sh);
+    }
+    if (threadIdx.x == 0) {
+        double r = s[0], im = s[1];
+        switch (y_pow) {
+        case 0: break;
+        case 1: { const double t = r; r = -im; im = t; break; }
+        case 2: r = -r; im = -im; break;
+        default: { const double t = r; r = im; im = -t; break; }
+        }
+        out[0] = r;
+        out[1] = im;
+    }
+}
+
+// Scratch of the allocation-free expectation (qs_expectation_noalloc): the
+// per-block partial sums of one Pauli expectation, two doubles for each of
+// at most kReduceBlocks blocks (32 KiB). Each GPU holds one copy from the
+// library's load until the process ends; calls that overlap on one GPU race
+// on it. Host code reaches it only through the per-device address that
+// hipGetSymbolAddress returns (the array's name is a host-side stand-in).
+constexpr size_t kNoAllocDoubles = 2 * size_t(kReduceBlocks);
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on `device`, resolved once per device with
+// that device current.
+int scratch_address(int device, double **out)
+{
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return fail(QS_EUNSUPPORTED, "device %d outside [0, %d)", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        QS_HIP(hipGetDevice(&cur));
+        if (cur != device) QS_HIP(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(QS_EDEVICE, "no device address for the expectation scratch");
+        addr[device] = static_cast<double *>(p);
+    }
+    *out = addr[device];
+    return QS_OK;
+}
+
 unsigned red_grid(uint64_t items)
 {
     uint64_t b = (items + kThreads - 1) / kThreads;
@@ -330,6 +389,34 @@ int reduce_pauli(qs_state *h, uint64_t xm, uint64_t ym, uint64_t zm, double *re,
     }
     *re = r;
     *im = i;
+    return QS_OK;
+}
+
+int reduce_pauli_noalloc(qs_state *h, uint64_t xm, uint64_t ym, uint64_t zm, double *device_out)
+{
+    double *part = nullptr;
+    if (int rc = scratch_address(h->device, &part)) return rc;
+    const uint64_t f = xm | ym;
+    const uint64_t sgn = ym | zm;
+    int hbit = 0;
+    uint64_t items = h->dim();
+    if (f) {
+        hbit = 63 - __builtin_clzll(f);
+        items >>= 1;
+    }
+    const unsigned g = red_grid(items);
+    if (size_t(g) * 2 > kNoAllocDoubles)
+        return fail(QS_EUNSUPPORTED, "%u partial sums exceed the %zu-double scratch", g, kNoAllocDoubles);
+    if (h->dtype == QS_C128)
+        hipLaunchKernelGGL(k_pauli<double>, dim3(g), dim3(kThreads), 0, h->stream,
+                           static_cast<const double2 *>(h->psi), items, f, hbit, sgn, part);
+    else
+        hipLaunchKernelGGL(k_pauli<float>, dim3(g), dim3(kThreads), 0, h->stream,
+                           static_cast<const float2 *>(h->psi), items, f, hbit, sgn, part);
+    QS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_pauli, dim3(1), dim3(kThreads), 0, h->stream, part, int(g),
+                       __builtin_popcountll(ym) & 3, device_out);
+    QS_HIP(hipGetLastError());
     return QS_OK;
 }
 

@@ -92,6 +92,7 @@ _sig("qs_run_program_range", [_P, _P, _I, _I])
 _sig("qs_qpe_crossover_bits", [_D, _D, _D, _I, _I, C.POINTER(_I)])
 _sig("qs_unitary_eig_residual", [_P, C.POINTER(_D)])
 _sig("qs_mlp_set_range", [_P, _P, _P])
+_sig("qs_expectation_noalloc", [_P, _U64, _U64, _U64, _P])
 _sig("qs_mlp_choose_stats", [_P, _P])
 _sig("qs_program_block_kind", [_P, _I, C.POINTER(_I), C.POINTER(_D)])
 _sig("qs_program_free", [_P])
@@ -430,6 +431,11 @@ class State:
         out = _D()
         _chk(_L.qs_norm2(self._h, C.byref(out)))
         return out.value
+
+    def expectation_noalloc(self, device_out, x_mask=0, y_mask=0, z_mask=0):
+        """qs_expectation_noalloc: (re, im) written to device_out (a device
+        pointer to 2 doubles) on the state's stream; nothing is allocated."""
+        _chk(_L.qs_expectation_noalloc(self._h, int(x_mask), int(y_mask), int(z_mask), device_out))
 
     def expectation(self, x_mask=0, y_mask=0, z_mask=0):
         re, im = _D(), _D()
