@@ -585,6 +585,10 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     register and LDS-staged dense sweeps: bit 0 nontemporal (streaming)
  *     stores, bit 1 nontemporal loads; 0 plain accesses.
  *   QS_TUNE_FFT_NT (dtype, -, -, n bucket): the same for the FFT passes.
+ *   QS_TUNE_MODMUL_KERNEL (dtype, -, -, -): controlled modular
+ *     multiplication with the work register at qubit 0: 0 or 4 the tiled
+ *     gather with 64 x 64 tiles (default), 3 with 64 x 32 tiles, 2 with
+ *     64 x 16 tiles, 1 the plain per-amplitude gather.
  *   QS_TUNE_GEMM_LIB (-, -, -, -): complex products of the dense-unitary
  *     route (squaring, controlled powers, the eigensolver route's
  *     products): 0 the library's own matrix-core kernel, 1 rocBLAS (a
@@ -598,7 +602,7 @@ enum qs_tune_param { QS_TUNE_SWEEP_PATH = 0, QS_TUNE_SWEEP_WG_PER_CU = 1, QS_TUN
                      QS_TUNE_FFT_LDS_KB = 3, QS_TUNE_MFMA_WG_PER_CU = 4,
                      QS_TUNE_BATCH_GANG_SHARE = 5, QS_TUNE_BATCH_BARRIER_AMPS = 6,
                      QS_TUNE_FFT_KERNEL = 7, QS_TUNE_SWEEP_NT = 8, QS_TUNE_FFT_NT = 9,
-                     QS_TUNE_GEMM_LIB = 10, QS_TUNE_COUNT = 11 };
+                     QS_TUNE_GEMM_LIB = 10, QS_TUNE_MODMUL_KERNEL = 11, QS_TUNE_COUNT = 12 };
 /* Target classes: lowest target inside a 128-byte line, inside a wave's
  * 64 consecutive amplitudes, or above bit 5. */
 enum qs_tune_class { QS_TCLS_SUBLINE = 0, QS_TCLS_SUBWAVE = 1, QS_TCLS_HIGH = 2 };

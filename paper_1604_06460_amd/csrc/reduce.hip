@@ -120,10 +120,12 @@ __device__ __forceinline__ uint32_t outcome_of(uint64_t i, const QArgs &qa)
 }
 
 // Marginals, small m: per-workgroup histogram in LDS, one row of partials
-// per workgroup. A wave covers 64 consecutive, 64-aligned indices, so when
-// every measured qubit is 6 or above (wave_uniform) all its lanes fall in
-// one bin: the wave sums its 64 probabilities first and adds them with one
-// LDS atomic, instead of 64 atomics on one address that the LDS serialises.
+// per workgroup. Workgroup b sweeps one contiguous chunk of the state, 256
+// consecutive amplitudes per step, so a thread's outcome changes only when
+// a measured qubit at bit 8 or above flips: the thread accumulates in a
+// register and adds to the LDS bin only when its outcome changes. When
+// every measured qubit is 6 or above (wave_uniform) all 64 lanes of a wave
+// share the outcome, and the wave sums its lanes before one atomic.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_hist_lds(const typename V2<R>::T *__restrict__ psi,
                                                        uint64_t dim, QArgs qa, int wave_uniform,
@@ -133,20 +135,32 @@ __global__ __launch_bounds__(kThreads) void k_hist_lds(const typename V2<R>::T *
     const int M = 1 << qa.m;
     for (int o = threadIdx.x; o < M; o += kThreads) hist[o] = 0.0;
     __syncthreads();
-    if (wave_uniform) {
-        for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < dim;
-             i += uint64_t(gridDim.x) * kThreads) {
-            const double x = double(psi[i].x), y = double(psi[i].y);
-            const double s = wave_sum(fma(x, x, y * y));
-            if ((threadIdx.x & 63) == 0) atomicAdd(&hist[outcome_of(i, qa)], s);
+    const uint64_t chunk = (dim + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo = uint64_t(blockIdx.x) * chunk;
+    const uint64_t hi = lo + chunk < dim ? lo + chunk : dim;
+    uint32_t cur = 0;
+    double acc = 0.0;
+    bool any = false;
+    auto flush = [&]() {
+        if (wave_uniform) {
+            const double s = wave_sum(acc);
+            if ((threadIdx.x & 63) == 0) atomicAdd(&hist[cur], s);
+        } else {
+            atomicAdd(&hist[cur], acc);
         }
-    } else {
-        for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < dim;
-             i += uint64_t(gridDim.x) * kThreads) {
-            const double x = double(psi[i].x), y = double(psi[i].y);
-            atomicAdd(&hist[outcome_of(i, qa)], fma(x, x, y * y));
+    };
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+        const double x = double(psi[i].x), y = double(psi[i].y);
+        const uint32_t o = outcome_of(i, qa);
+        if (any && o != cur) {       // wave-uniform when wave_uniform is set
+            flush();
+            acc = 0.0;
         }
+        cur = o;
+        any = true;
+        acc = fma(x, x, fma(y, y, acc));
     }
+    if (any) flush();
     __syncthreads();
     for (int o = threadIdx.x; o < M; o += kThreads) partial[size_t(blockIdx.x) * M + o] = hist[o];
 }
@@ -466,9 +480,9 @@ int measure(qs_state *h, int m, const int *qubits, int shots, const double *u, u
         const size_t lds = sizeof(double) * size_t(M);
         int lowest = 64;
         for (int r = 0; r < m; ++r) lowest = std::min(lowest, qubits[r]);
-        // wave-uniform bins need 64-aligned waves: the grid stride is a
-        // multiple of 256, and a state below 64 amplitudes has one partial wave
-        const int uniform = (lowest >= 6 && h->dim() >= 64) ? 1 : 0;
+        // wave-uniform bins need whole 64-aligned waves: chunks are powers of
+        // two of at least 256 amplitudes once the state has 128 or more
+        const int uniform = (lowest >= 6 && h->dim() >= 128) ? 1 : 0;
         if (h->dtype == QS_C128)
             hipLaunchKernelGGL(k_hist_lds<double>, dim3(g), dim3(kThreads), lds, h->stream,
                                static_cast<const double2 *>(h->psi), h->dim(), qa, uniform, part);

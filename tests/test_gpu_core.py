@@ -30,8 +30,9 @@ def _state(Q, S, n, dtype, seed):
     st = Q.State(n, dtype)
     psi = S.normal_state(n, seed)
     st.set(psi)
-    # the oracle starts from exactly what the GPU holds
-    return st, st.get().astype(np.complex128)
+    # the oracle starts from exactly what the GPU holds: the input rounded
+    # to the state's precision on the host
+    return st, psi.astype(st.np_dtype).astype(np.complex128)
 
 
 def _err(a, b):
@@ -294,6 +295,37 @@ def test_modmul_bit_exact(Q, O, S, dtype, w, c, work_lo, ctrl_lo, n, seed):
     ref = O.modmul(psi, work_lo, w, ctrl_lo, c, a, N).astype(st.np_dtype)
     got = st.get()
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+@pytest.mark.parametrize("w,c,ctrl_lo,n,a,N", [
+    (15, 3, 15, 19, None, None),        # seeded a, N just above 2^14
+    (16, 4, 17, 21, 2, 65521),          # a = 2: small powers give short gaps (plain blocks) next to tiled ones
+    (16, 2, 16, 19, 65520, 65521),      # a = N - 1: gaps of 1 and N - 1 in every block
+    (17, 5, 18, 24, 3, 131071),         # spectator qubits between and above the registers
+    (20, 1, 20, 22, None, None)])
+def test_modmul_tiled_gather_bit_exact(Q, O, S, dtype, w, c, ctrl_lo, n, a, N):
+    """The tiled gather (work register at qubit 0, three-gap rows of 1024
+    points per control value) against the oracle and against the plain
+    per-amplitude gather, bit for bit; multipliers whose rows degenerate
+    fall back to the plain gather per control block."""
+    if a is None:
+        a, N = S.modmul_params(w, 1000 + w)
+    st, psi = _state(Q, S, n, dtype, 17 + n)
+    st.emulate_modmul(0, w, ctrl_lo, c, a, N)
+    got = st.get()
+    ref = O.modmul(psi, 0, w, ctrl_lo, c, a, N).astype(st.np_dtype)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+    try:
+        for kern in (1, 2, 3):      # plain gather, 64 x 16 and 64 x 32 tiles
+            Q.tune_set(Q.QS_TUNE_MODMUL_KERNEL, kern)
+            st.set(psi)
+            st.emulate_modmul(0, w, ctrl_lo, c, a, N)
+            other = st.get()
+            assert np.array_equal(got.view(np.uint8), other.view(np.uint8)), kern
+    finally:
+        Q.tune_set(Q.QS_TUNE_MODMUL_KERNEL, 0)
+    st.free()
 
 
 def test_table_permutation_bit_exact(Q, O, S):
