@@ -578,9 +578,14 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     workgroup, 1..256.
  *   QS_TUNE_BATCH_BARRIER_AMPS (-, -, -, -): cost of a gang barrier, in
  *     amplitude-op units, used to order the batch queue.
- *   QS_TUNE_FFT_KERNEL (dtype, -, -, n bucket): FFT pass kernel: 1 one
- *     workgroup per tile (default), 2 persistent workgroups that prefetch
- *     the next tile into registers.
+ *   QS_TUNE_FFT_KERNEL (dtype, -, -, n bucket): FFT pass kernel. Passes
+ *     with a 10-bit digit: 0 or 4 persistent workgroups holding a register
+ *     tile of 128-byte rows and prefetching the next one (default), 3 one
+ *     workgroup per register tile, 5 persistent register tiles with eight
+ *     values per thread (1024-thread workgroups). Other passes, and every
+ *     pass under 1 or 2: an LDS tile per workgroup (1), or persistent
+ *     workgroups streaming LDS tiles (2). The register-tile kernels ignore
+ *     the cache-policy option.
  *   QS_TUNE_SWEEP_NT (dtype, k, class, n bucket): cache policy of the
  *     register and LDS-staged dense sweeps: bit 0 nontemporal (streaming)
  *     stores, bit 1 nontemporal loads; 0 plain accesses.

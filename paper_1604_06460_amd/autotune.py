@@ -160,15 +160,17 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
 def tune_fft(timer, dtype, n, nb, reps, margin, log):
     st = Q.State(n, dtype, stream=timer.stream.cuda_stream)
     times = {}
-    for kern in (1, 2):
-        for digit in (7, 8, 9, 10):
-            for kb in (40, 80, 160):
-                Q.tune_set(Q.QS_TUNE_FFT_KERNEL, kern, dtype, 0, 0, nb)
-                Q.tune_set(Q.QS_TUNE_FFT_DIGIT, digit, dtype, 0, 0, nb)
-                Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, kb, dtype, 0, 0, nb)
-                times[(kern, digit, kb)] = timer.ms(lambda: st.emulate_qft(0, n), reps)
+    # LDS-tile kernels over digit widths and tile budgets; the register-tile
+    # kernels (10-bit digits, their own LDS use) once each
+    cands = [(kern, digit, kb) for kern in (1, 2) for digit in (7, 8, 9, 10) for kb in (40, 80, 160)]
+    cands += [(kern, 10, 80) for kern in (3, 4, 5)]
+    for kern, digit, kb in cands:
+        Q.tune_set(Q.QS_TUNE_FFT_KERNEL, kern, dtype, 0, 0, nb)
+        Q.tune_set(Q.QS_TUNE_FFT_DIGIT, digit, dtype, 0, 0, nb)
+        Q.tune_set(Q.QS_TUNE_FFT_LDS_KB, kb, dtype, 0, 0, nb)
+        times[(kern, digit, kb)] = timer.ms(lambda: st.emulate_qft(0, n), reps)
     st.free()
-    dflt = (1, 10, 80)
+    dflt = (4, 10, 80)
     best = _pick(times, dflt, margin)
     vals = best if best != dflt else (0, 0, 0)
     Q.tune_set(Q.QS_TUNE_FFT_KERNEL, vals[0], dtype, 0, 0, nb)

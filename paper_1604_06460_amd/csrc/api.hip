@@ -286,6 +286,7 @@ int qs_free(qs_handle h)
     if (!h->borrowed && h->psi) (void)hipFree(h->psi);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->partials) (void)hipFree(h->partials);
+    if (h->fft_roots) (void)hipFree(h->fft_roots);
     if (h->host_out) (void)hipHostFree(h->host_out);
     h->stage.release();
     delete h;

@@ -391,8 +391,12 @@ inline void stage_plan(int r, PassArgs &pa, int max_rho = 4)
     }
 }
 
+// reg_cb >= 0 asks for exactly reg_cb column bits on every pass whose digit
+// is kRmax bits wide (the register-tile kernels), where the state has that
+// many bits outside the digit; other passes size their columns to the LDS
+// budget.
 inline int plan_passes(int n, int q_lo, int m, int inverse, int digit, size_t lds_budget, size_t amp,
-                       std::vector<PassArgs> &out, int max_rho = 4)
+                       std::vector<PassArgs> &out, int max_rho = 4, int reg_cb = -1)
 {
     const int P = (m + digit - 1) / digit;
     if (P > 8) return fail(QS_EUNSUPPORTED, "QFT field needs more than 8 passes");
@@ -423,7 +427,9 @@ inline int plan_passes(int n, int q_lo, int m, int inverse, int digit, size_t ld
         const bool last = (j == P - 1);
         int maxcb = 0;
         while ((2 << maxcb) <= kMaxCols && lds_need(pa.r, maxcb + 1, amp) <= lds_budget) ++maxcb;
-        const int want = std::max(0, std::min(maxcb, n - pa.r));
+        int want = std::max(0, std::min(maxcb, n - pa.r));
+        const int avail = (last && P > 1) ? q_lo + width[0] : n - pa.r;
+        if (reg_cb >= 0 && pa.r == kRmax && avail >= reg_cb) want = reg_cb;
         std::vector<int> cols;
         if (last && P > 1) {
             // destination-contiguous bits: spectators below the field, then the

@@ -57,6 +57,7 @@ struct qs_state {
     qs::Staging stage;
     double *partials = nullptr; // reduction partials (device)
     size_t partials_cap = 0;
+    void *fft_roots = nullptr;  // root tables of the register-tile FFT passes (device)
     double *host_out = nullptr; // pinned host landing area for small results
     size_t host_out_cap = 0;
     size_t amp_bytes() const { return dtype == QS_C128 ? 16 : 8; }

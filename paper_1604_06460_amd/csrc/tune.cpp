@@ -32,7 +32,7 @@ Range range_of(int p)
     case QS_TUNE_MFMA_WG_PER_CU: return {1, 16};
     case QS_TUNE_BATCH_GANG_SHARE: return {1, 256};
     case QS_TUNE_BATCH_BARRIER_AMPS: return {1, 1 << 24};
-    case QS_TUNE_FFT_KERNEL: return {1, 2};
+    case QS_TUNE_FFT_KERNEL: return {1, 5};
     case QS_TUNE_SWEEP_NT: return {1, 3};
     case QS_TUNE_FFT_NT: return {1, 3};
     case QS_TUNE_GEMM_LIB: return {1, 1};

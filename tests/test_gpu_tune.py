@@ -111,6 +111,27 @@ def test_every_fft_shape_matches_oracle(Q, O, S, dtype):
                 assert np.abs(got - ref).max() < TOL[dtype], (dtype, q_lo, m, digit, kb)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_every_fft_kernel_matches_oracle(Q, O, S, dtype):
+    """Every pass kernel the FFT option selects, on fields with 10-bit
+    digits (the register-tile kernels) and without: forward and inverse,
+    spectator qubits below and above the field, single and final passes."""
+    cases = ((20, 0, 20, False), (20, 0, 20, True), (22, 5, 10, False), (22, 2, 20, True),
+             (21, 0, 20, False), (21, 1, 10, True), (20, 3, 17, False))
+    for n, q_lo, m, inv in cases:
+        psi0 = S.normal_state(n, 40 + n + q_lo)
+        ref = O.dft_numpy(psi0, q_lo, m, inv)
+        for kern in (1, 2, 3, 4, 5):
+            Q.tune_set(Q.QS_TUNE_FFT_KERNEL, kern, dtype)
+            st = Q.State(n, dtype)
+            st.set(psi0)
+            st.emulate_qft(q_lo, m, inverse=inv)
+            got = st.get().astype(np.complex128)
+            st.free()
+            err = float(np.abs(got - ref).max())
+            assert err < TOL[dtype], (dtype, kern, n, q_lo, m, inv, err)
+
+
 def test_mfma_grid_sizes_match_oracle(Q, O, S):
     n = 18
     rng = np.random.default_rng(5)
