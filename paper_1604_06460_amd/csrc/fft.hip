@@ -12,31 +12,41 @@
 // top)) and stores output digit l_j in the digit's place. After the last
 // pass the output digits sit in reversed digit order; the last pass writes
 // out of place and performs that reversal in its store, so a P-pass
-// transform moves the state P times.
+// transform moves the state P times. The passes alternate between the
+// state and a scratch buffer so that the last one lands in the state.
 //
-// Inside a pass a workgroup holds a tile of 2^r digit values x C columns
-// (C consecutive values of the lowest available bits, so global accesses run
-// in C-element segments; the default 80 KB tile gives a 10-bit digit C = 4
-// complex128 or 8 complex64 columns, 64 bytes, and the whole LDS of a CU one
-// full 128-byte line) in LDS and performs the 2^r-point DFT as radix-2^rho
-// register stages (rho <= 3 for complex128, 4 for complex64), again
-// decimation in frequency.
+// Passes over a 10-bit digit (every pass of a 30-qubit QFT) run on
+// register-tile kernels: a tile is the 1024 digit values of C columns with
+// C amplitudes = 128 bytes per row (8 complex128, 16 complex64), the
+// shortest row that a DRAM burst serves in full; rows of the top digit lie
+// 16 MiB apart. The tile is held in registers, and LDS serves only the
+// exchanges of the 16 x 64 (or 8 x 128) split of the 1024-point DFT. The
+// default (k_fft_reg_stream) is persistent, one workgroup per CU: it
+// transforms one tile while the next one loads into registers. The
+// register-tile kernels are described with their code below.
 //
-// Launch: one workgroup per tile (k_fft_pass, the default; two workgroups
-// share a CU with the 80 KB tile) in an XCD-aware order. A persistent
-// alternative (k_fft_stream, tuning option 2) walks a contiguous range of
-// tiles and prefetches the next tile into registers while the current one is
-// transformed; it needs more registers and is slower here. The LDS layout
-// is column-major with a 4-element pad per column and the low 4 bits of the
-// row XOR-swizzled by the next 4, which keeps both the strided and the
-// contiguous stage accesses free of bank conflicts.
+// Other passes (and every pass under FFT kernel options 1 and 2) use an
+// LDS tile of 2^r digit values x C columns (C consecutive values of the
+// lowest available bits; the 80 KB budget gives a 10-bit digit C = 4
+// complex128 or 8 complex64 columns, 64 bytes) and perform the 2^r-point
+// DFT as radix-2^rho register stages (rho <= 3 for complex128, 4 for
+// complex64), again decimation in frequency: one workgroup per tile
+// (k_fft_pass) in an XCD-aware order, or persistent workgroups streaming
+// tiles (k_fft_stream). Their LDS layout is column-major with a 4-element
+// pad per column and the low 4 bits of the row XOR-swizzled by the next 4,
+// which keeps both the strided and the contiguous stage accesses free of
+// bank conflicts.
 //
-// Twiddles are products of two table entries held in LDS. Stage twiddles:
-// exp(s 2 pi i y / 1024) = A[y mod 32] * B[y / 32]. Pass twiddles: per
-// column, exp(s 2 pi i k_rest l / N_j) = GA[l mod 32] * GB[l / 32] with the
-// exponents k_rest * l reduced exactly in integers before the angle is
-// formed. Every table entry is one FP64 sincospi call; FP32 states round
-// the FP64 values. The device code lives in fft_dev.h (shared with the
+// Twiddles. LDS-tile kernels: products of two table entries in LDS (stage:
+// exp(s 2 pi i y / 1024) = A[y mod 32] * B[y / 32]; pass: per column
+// GA[l mod 32] * GB[l / 32]). Register-tile kernels: butterfly twiddles of
+// the 8- and 16-point DFTs are compile-time constants, the inter-stage
+// twiddles are powers of one per-thread root, and the pass twiddle is the
+// product of a per-pass column table and a per-tile table. The exponents
+// (k_rest * l) are always reduced exactly in integers before an angle is
+// formed; every table entry and root is one FP64 sincospi call or a
+// product of such entries, and FP32 states round the FP64 values. The
+// device code of the LDS-tile kernels lives in fft_dev.h (shared with the
 // batched kernel).
 #include "fft_dev.h"
 
@@ -152,6 +162,13 @@ __device__ __forceinline__ float2 copy_reg(float2 x)
 // workgroups per CU) or the whole tile at once (k_fft_reg_stream). Output
 // digit k1 + 16 k2 gets the pass twiddle and is stored in the digit's place,
 // or at its reversed-digit destination on a final pass.
+//
+// Memory ordering in the persistent kernels: the vector-memory counter
+// counts loads and stores together and completes in order, so any global
+// load issued inside the tile loop after a tile's stores would make its
+// consumer wait for those stores. The loop therefore issues exactly one
+// batch of global loads per tile (the next tile's values, right at the top)
+// and reads every twiddle root from LDS tables built once per workgroup.
 constexpr int kRegCols128 = 8;    // complex128: 8 columns of 16 bytes
 constexpr int kRegCols64 = 16;    // complex64: 16 columns of 8 bytes
 template <typename R> struct RegCols { static constexpr int value = kRegCols128; };
@@ -793,11 +810,21 @@ int run_fft(qs_state *h, int q_lo, int m, int inverse)
     const int P = int(passes.size());
     if (P > 1)
         if (int rc = ensure_scratch(h)) return rc;
+    // With P > 1 the last passes alternate between the state and the scratch
+    // buffer, an even number of them, so the last (which reverses the digits
+    // and cannot run in place) writes the state itself; an odd leading pass
+    // runs in place. Out-of-place passes are also faster than in-place ones
+    // at the middle digit's stride, and no copy back is needed.
+    const int k_oop = P > 1 ? (P & ~1) : 0;
+    C2 *cur = static_cast<C2 *>(h->psi), *oth = static_cast<C2 *>(h->scratch);
     for (int j = 0; j < P; ++j) {
         const PassArgs &pa = passes[size_t(j)];
-        const bool last = (j == P - 1);
-        const C2 *src = static_cast<const C2 *>(h->psi);
-        C2 *dst = (last && P > 1) ? static_cast<C2 *>(h->scratch) : static_cast<C2 *>(h->psi);
+        const C2 *src = cur;
+        C2 *dst = cur;
+        if (j >= P - k_oop) {
+            dst = oth;
+            std::swap(cur, oth);
+        }
         const size_t lds = pass_lds_bytes(pa, sizeof(C2));
         const uint64_t elems = uint64_t(1) << (pa.r + pa.cb);
         if (reg && pa.r == kRmax && pa.cb == reg_cb) {
@@ -837,14 +864,6 @@ int run_fft(qs_state *h, int q_lo, int m, int inverse)
                                h->stream, src, dst, pa);
         }
         QS_HIP(hipGetLastError());
-    }
-    if (P > 1) {
-        if (h->borrowed) {
-            QS_HIP(hipMemcpyAsync(h->psi, h->scratch, h->dim() * h->amp_bytes(),
-                                  hipMemcpyDeviceToDevice, h->stream));
-        } else {
-            std::swap(h->psi, h->scratch);
-        }
     }
     return QS_OK;
 }
