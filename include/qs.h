@@ -591,9 +591,10 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     stores, bit 1 nontemporal loads; 0 plain accesses.
  *   QS_TUNE_FFT_NT (dtype, -, -, n bucket): the same for the FFT passes.
  *   QS_TUNE_MODMUL_KERNEL (dtype, -, -, -): controlled modular
- *     multiplication with the work register at qubit 0: 0 or 4 the tiled
- *     gather with 64 x 64 tiles (default), 3 with 64 x 32 tiles, 2 with
- *     64 x 16 tiles, 1 the plain per-amplitude gather.
+ *     multiplication with the work register at qubit 0: 0 or 5 the tiled
+ *     gather with 64 x 128 tiles in 1024-thread workgroups (default), 4
+ *     with 64 x 64 tiles, 3 with 64 x 32, 2 with 64 x 16 (512 or 256
+ *     threads), 1 the plain per-amplitude gather.
  *   QS_TUNE_GEMM_LIB (-, -, -, -): complex products of the dense-unitary
  *     route (squaring, controlled powers, the eigensolver route's
  *     products): 0 the library's own matrix-core kernel, 1 rocBLAS (a

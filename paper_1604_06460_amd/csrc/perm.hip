@@ -34,6 +34,13 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t x, uint64_t y, uint64_t N, u
     return r;
 }
 
+// (x + y) mod N for x, y < N
+__device__ __forceinline__ uint64_t addmod(uint64_t x, uint64_t y, uint64_t N)
+{
+    const uint64_t s = x + y;
+    return s >= N ? s - N : s;
+}
+
 // inv_pow[c] = a^(-c) mod N for c in [0, 2^cbits): ainv = a^(-1) mod N by
 // the extended Euclidean algorithm, then square-and-multiply.
 __global__ void k_inv_powers(uint64_t a, uint64_t N, uint64_t mu, int count,
@@ -106,7 +113,10 @@ __global__ __launch_bounds__(kThreads) void k_modmul_gather(
 // their columns, so every block keeps 64 busy workgroups) and walks them
 // COLS outputs at a time through an LDS tile: COLS reads of 64 consecutive
 // sources, 64 writes of COLS consecutive outputs, each row continued by the
-// next tile of the same workgroup. Indices
+// next tile of the same workgroup. The default tile is 64 x 128 (1024
+// threads; 130 KB of LDS for complex128, one workgroup per CU): its writes
+// run over 2 KB (complex128), which pays more than longer reads (128 x 64
+// tiles are slower). Indices
 // x >= N are fixed points and are copied. A control value without a
 // convergent denominator in [64, min(4096, N / 64)] keeps the plain gather
 // for its blocks.
@@ -132,14 +142,14 @@ __device__ __forceinline__ uint64_t row_len(uint32_t j, const ModRows &r)
 // grid: kWgPerBlock workgroups per control block (a block = 2^w consecutive
 // amplitudes sharing all other bits); workgroups past the block's rows only
 // copy their share of the fixed points. NT threads.
-template <typename R, int COLS, int NT>
+template <typename R, int COLS, int NT, int ROWS = kTileRows>
 __global__ __launch_bounds__(NT) void k_modmul_tiled(const typename V2<R>::T *__restrict__ in,
                                                       typename V2<R>::T *__restrict__ out, ModmulArgs ma,
                                                       const ModRows *__restrict__ rows)
 {
     using C2 = typename V2<R>::T;
     constexpr int kTileCols = COLS, kThreads = NT;
-    __shared__ C2 tile[kTileCols][kTileRows + 1];
+    __shared__ C2 tile[kTileCols][ROWS + 1];
     const uint64_t blk = blockIdx.x / kWgPerBlock;
     const uint32_t jb = blockIdx.x % kWgPerBlock;
     const uint64_t base = blk << ma.w;
@@ -161,61 +171,69 @@ __global__ __launch_bounds__(NT) void k_modmul_tiled(const typename V2<R>::T *__
         for (uint64_t y = lo + t; y < hi; y += kThreads) out[base + y] = in[base + mulmod(r.B, y, N, ma.mu)];
         return;
     }
-    // the block's rows form nrb groups of 64; when there are fewer than 64
+    // the block's rows form nrb groups of ROWS; when there are fewer than 64
     // groups, each group's columns are split into seg = 64 / nrb segments so
     // that all 64 workgroups of the block carry work
-    const uint32_t nrb = (r.R + kTileRows - 1) / kTileRows;
+    const uint32_t nrb = (r.R + ROWS - 1) / ROWS;
     const uint32_t nseg = kWgPerBlock / nrb;
     if (jb >= nrb * nseg) return;
-    const uint32_t j0 = (jb % nrb) * kTileRows, sg = jb / nrb;
-    const uint32_t j1 = min(r.R, j0 + kTileRows);
+    const uint32_t j0 = (jb % nrb) * ROWS, sg = jb / nrb;
+    const uint32_t j1 = min(r.R, j0 + ROWS);
     // longest row of the group: rows have one of two lengths
     uint64_t maxlen = 0;
     for (uint32_t j = j0; j < j1; ++j) maxlen = max(maxlen, row_len(j, r));
     const uint64_t ntiles = (maxlen + kTileCols - 1) / kTileCols;
     const uint64_t tlo = ntiles * sg / nseg, thi = ntiles * (sg + 1) / nseg;
-    // element e of a tile: load view (col = e / 64, row = e % 64), store
+    // element e of a tile: load view (col = e / ROWS, row = e % ROWS), store
     // view (row = e / COLS, col = e % COLS). The next tile's sources are
     // loaded into registers while the current tile is written out.
-    constexpr int kPer = kTileRows * kTileCols / kThreads;
+    //
+    // Index arithmetic without a product per element: a thread's load
+    // elements share row j = j0 + t mod ROWS and step the column by
+    // NT / ROWS, so their sources j + B i step by B (NT / ROWS) mod N; its store
+    // elements share column t mod COLS and step the row by NT / COLS, so
+    // their destinations P_j + i step by A (NT / COLS) mod N. From tile to
+    // tile the sources advance by B COLS and the destinations by COLS. One
+    // modular product per thread sets each chain up.
+    constexpr int kPer = ROWS * kTileCols / kThreads;
+    constexpr int kLStep = kThreads / ROWS, kSStep = kThreads / kTileCols;
+    const uint32_t lrow = uint32_t(t) % ROWS, lcol = uint32_t(t) / ROWS;
+    const uint32_t jl = j0 + lrow;
+    const uint64_t llen = jl < j1 ? row_len(jl, r) : 0;
+    const uint64_t lstep = mulmod(r.B, kLStep, N, ma.mu), ltile = mulmod(r.B, kTileCols, N, ma.mu);
+    const uint32_t srow = uint32_t(t) / kTileCols, scol = uint32_t(t) % kTileCols;
+    const uint64_t sstep = mulmod(r.A, kSStep, N, ma.mu);
+    // chain heads at tile tlo: source of load element 0, destination of store element 0
+    uint64_t xh = addmod(mulmod(r.B, tlo * kTileCols + lcol, N, ma.mu), uint64_t(jl) % N, N);
+    uint64_t yh = addmod(mulmod(uint64_t(j0 + srow), r.A, N, ma.mu), (tlo * kTileCols + scol) % N, N);
     C2 pre[kPer];
-    auto fetch = [&](uint64_t i0) {
+    auto fetch = [&](uint64_t i0, uint64_t x) {
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const int e = t + q * kThreads;
-            const int col = e / kTileRows, row = e % kTileRows;
-            const uint32_t j = j0 + uint32_t(row);
-            const uint64_t i = i0 + uint64_t(col);
-            if (j < j1 && i < row_len(j, r)) {
-                uint64_t x = mulmod(r.B, i, N, ma.mu) + j;     // j + B i mod N
-                if (x >= N) x -= N;
-                pre[q] = in[base + x];
-            } else {
-                pre[q] = C2{R(0), R(0)};                        // never stored
-            }
+            const uint64_t i = i0 + lcol + uint64_t(q) * kLStep;
+            pre[q] = i < llen ? in[base + x] : C2{R(0), R(0)};   // zeros are never stored
+            x = addmod(x, lstep, N);
         }
     };
-    if (tlo < thi) fetch(tlo * kTileCols);
+    if (tlo < thi) fetch(tlo * kTileCols, xh);
     for (uint64_t i0 = tlo * kTileCols; i0 < thi * kTileCols; i0 += kTileCols) {
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int e = t + q * kThreads;
-            tile[e / kTileRows][e % kTileRows] = pre[q];
+            tile[e / ROWS][e % ROWS] = pre[q];
         }
         __syncthreads();
-        if (i0 + kTileCols < thi * kTileCols) fetch(i0 + kTileCols);
+        xh = addmod(xh, ltile, N);
+        if (i0 + kTileCols < thi * kTileCols) fetch(i0 + kTileCols, xh);
+        uint64_t y = yh;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const int e = t + q * kThreads;
-            const int row = e / kTileCols, col = e % kTileCols;
-            const uint32_t j = j0 + uint32_t(row);
-            const uint64_t i = i0 + uint64_t(col);
-            if (j < j1 && i < row_len(j, r)) {
-                uint64_t y = mulmod(uint64_t(j), r.A, N, ma.mu) + i;   // P_j + i mod N
-                if (y >= N) y -= N;
-                out[base + y] = tile[col][row];
-            }
+            const uint32_t row = srow + uint32_t(q) * kSStep;
+            const uint32_t j = j0 + row;
+            if (j < j1 && i0 + scol < row_len(j, r)) out[base + y] = tile[scol][row];
+            y = addmod(y, sstep, N);
         }
+        yh = addmod(yh, kTileCols % N, N);
         __syncthreads();
     }
 }
@@ -479,8 +497,10 @@ void launch_tiled(qs_state *h, int kern, unsigned blocks, const ModmulArgs &ma, 
         hipLaunchKernelGGL((k_modmul_tiled<R, 16, 256>), dim3(blocks), dim3(256), 0, h->stream, src, dst, ma, tab);
     else if (kern == 3)
         hipLaunchKernelGGL((k_modmul_tiled<R, 32, 512>), dim3(blocks), dim3(512), 0, h->stream, src, dst, ma, tab);
-    else
+    else if (kern == 4)
         hipLaunchKernelGGL((k_modmul_tiled<R, 64, 512>), dim3(blocks), dim3(512), 0, h->stream, src, dst, ma, tab);
+    else
+        hipLaunchKernelGGL((k_modmul_tiled<R, 128, 1024>), dim3(blocks), dim3(1024), 0, h->stream, src, dst, ma, tab);
 }
 
 // Row tables of the tiled gather, per control value c: A = a^c mod N, its

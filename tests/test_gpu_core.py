@@ -305,9 +305,9 @@ def test_modmul_bit_exact(Q, O, S, dtype, w, c, work_lo, ctrl_lo, n, seed):
     (17, 5, 18, 24, 3, 131071),         # spectator qubits between and above the registers
     (20, 1, 20, 22, None, None)])
 def test_modmul_tiled_gather_bit_exact(Q, O, S, dtype, w, c, ctrl_lo, n, a, N):
-    """The tiled gather (work register at qubit 0, three-gap rows of 1024
-    points per control value) against the oracle and against the plain
-    per-amplitude gather, bit for bit; multipliers whose rows degenerate
+    """The tiled gather (work register at qubit 0, three-gap rows per
+    control value; default 64 x 128 tiles) against the oracle and against
+    the plain per-amplitude gather and the narrower tiles, bit for bit; multipliers whose rows degenerate
     fall back to the plain gather per control block."""
     if a is None:
         a, N = S.modmul_params(w, 1000 + w)
@@ -317,7 +317,7 @@ def test_modmul_tiled_gather_bit_exact(Q, O, S, dtype, w, c, ctrl_lo, n, a, N):
     ref = O.modmul(psi, 0, w, ctrl_lo, c, a, N).astype(st.np_dtype)
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
     try:
-        for kern in (1, 2, 3):      # plain gather, 64 x 16 and 64 x 32 tiles
+        for kern in (1, 2, 3, 4):   # plain gather, 64 x 16, 64 x 32 and 64 x 64 tiles
             Q.tune_set(Q.QS_TUNE_MODMUL_KERNEL, kern)
             st.set(psi)
             st.emulate_modmul(0, w, ctrl_lo, c, a, N)
