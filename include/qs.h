@@ -515,20 +515,26 @@ int qs_qpe_crossover_bits(double t_apply, double t_build, double t_op, int per_b
 
 /* The eigensolver route of Sec. III-C: U = V diag(e^(i theta)) V^dagger,
  * after which every controlled power costs the same. The library's
- * eigensolver is Hermitian (rocSOLVER zheevd), so it is given
+ * eigensolver is Hermitian (rocSOLVER zheevd; zheev, QR iteration, as a
+ * retry when zheevd reports failure or its result leaves a non-finite
+ * residual, which it has done on highly degenerate input), so it is given
  * H = (U + U^dagger)/2 + beta (U - U^dagger)/(2i), beta = 0.4011..., which
- * has U's eigenvectors; each pair of neighbouring eigenvectors is then
- * rotated by the exact eigenvectors of its 2 x 2 block of V^dagger U V (even
- * pairs, then odd pairs), which separates eigenphases that H's eigenvalues
- * cos(theta) + beta sin(theta) confuse (mirror images about atan(beta)). theta_k
- * is the argument of the final diagonal, in (-pi, pi]. The result is checked:
- * the largest off-diagonal magnitude of V^dagger U V must not exceed 1e-10
- * (U's 2-norm is 1). A cluster of three or more confused phases (a phase
- * with a multiplicity plus its mirror image) is not separated by the pair
- * passes and fails this check: QS_EUNSUPPORTED, no decomposition is kept,
- * and the squaring route (qs_emulate_qpe_powers) still applies. Device
- * memory: three more 2^m x 2^m matrices during the call, V kept.
- * Synchronous; QS_EDEVICE if the eigensolver does not converge. */
+ * has U's eigenvectors. H's eigenvalues cos(theta) + beta sin(theta)
+ * confuse mirror images about atan(beta): a run of three or more (nearly)
+ * equal eigenvalues of H (a phase with a multiplicity plus its mirror image)
+ * spans an invariant subspace of U on which K = (B - B^dagger)/(2i),
+ * B = V^dagger U V restricted to the run, has eigenvalues sin(theta) that
+ * separate the two phases; K is diagonalised by the library's own cyclic
+ * Jacobi kernel (one workgroup, runs of up to 96) and the run's columns of
+ * V rotated by its eigenvectors. Each pair of neighbouring eigenvectors is
+ * then rotated by the exact eigenvectors of its 2 x 2 block of V^dagger U V
+ * (even pairs, then odd pairs). theta_k is the argument of the final
+ * diagonal, in (-pi, pi]. The result is checked: the largest off-diagonal
+ * magnitude of V^dagger U V must not exceed 1e-10 (U's 2-norm is 1);
+ * otherwise QS_EUNSUPPORTED, no decomposition is kept, and the squaring
+ * route (qs_emulate_qpe_powers) still applies. Device memory: three more
+ * 2^m x 2^m matrices during the call, V kept. Synchronous; QS_EDEVICE if
+ * an eigensolver does not converge. */
 int qs_unitary_eig(qs_unitary u);
 /* The largest off-diagonal magnitude of V^dagger U V measured by the last
  * qs_unitary_eig (also after it failed the check). QS_EINVAL for NULL

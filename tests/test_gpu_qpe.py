@@ -171,16 +171,16 @@ def test_eig_residual_of_the_ising_step(Q, O, S, m):
     u.free()
 
 
-@pytest.mark.parametrize("mult", [(2, 1), (1, 2), (3, 1), (2, 2)])
-def test_eig_mirror_cluster_with_multiplicity_fails_loudly(Q, O, S, mult):
+@pytest.mark.parametrize("m,mult", [(4, (2, 1)), (4, (1, 2)), (4, (3, 1)), (4, (2, 2)), (5, (5, 3)), (6, (20, 12))])
+def test_eig_mirror_clusters_are_resolved(Q, O, S, m, mult):
     """A phase with a multiplicity plus its mirror image about atan(beta):
-    three or more eigenvectors share one eigenvalue of the Hermitian blend,
-    and neighbouring-pair rotations may not separate them. The entry point
-    must then return QS_EUNSUPPORTED with the residual above the bar; when
-    it returns QS_OK the decomposition must be right."""
-    m, d = 4, 16
+    three or more eigenvectors share one eigenvalue of the Hermitian blend.
+    The cluster's K = (B - B^dagger)/(2i) separates the two phases, so the
+    decomposition must succeed with the residual under the bar and
+    reproduce U."""
+    d = 1 << m
     phi = np.arctan(BETA)
-    rng = np.random.default_rng(40 + 3 * mult[0] + mult[1])
+    rng = np.random.default_rng(40 + 3 * mult[0] + mult[1] + m)
     t1 = 1.1
     th = rng.uniform(-np.pi, np.pi, d)
     th[:mult[0]] = t1
@@ -190,20 +190,34 @@ def test_eig_mirror_cluster_with_multiplicity_fails_loudly(Q, O, S, mult):
     gates = [S.Gate(tuple(range(m)), M)]
     U = O.block_matrix(m, gates)
     u = Q.Unitary(gates, m)
-    try:
-        u.eig()
-    except Q.QSError as e:
-        assert e.status == Q.QS_EUNSUPPORTED, e
-        r = u.eig_residual()
-        print("mult %s: rejected, residual %.3e" % (mult, r))
-        assert r > 1e-10
-        with pytest.raises(Q.QSError):
-            u.eig_get()                          # nothing kept
-    else:
-        r = u.eig_residual()
-        print("mult %s: resolved, residual %.3e" % (mult, r))
-        assert r <= 1e-10
-        _check_eig(u, U, 1e-9)
+    u.eig()
+    r = u.eig_residual()
+    print("m %d mult %s: residual %.3e" % (m, mult, r))
+    assert r <= 1e-10
+    _check_eig(u, U, 1e-9)
+    u.free()
+
+
+def test_eig_cluster_of_seventy_is_resolved(Q, O, S):
+    """A cluster of 70 coinciding blend eigenvalues (K alone fills 78 KB of
+    LDS): a 6-qubit gate with 20 copies of one phase and 15 of its mirror
+    image, in a 7-qubit register (each eigenphase doubles)."""
+    m, d6 = 7, 64
+    phi = np.arctan(BETA)
+    rng = np.random.default_rng(77)
+    th = rng.uniform(-np.pi, np.pi, d6)
+    th[:20] = 0.7
+    th[20:35] = 2 * phi - 0.7
+    q, _ = np.linalg.qr(rng.standard_normal((d6, d6)) + 1j * rng.standard_normal((d6, d6)))
+    M = (q * np.exp(1j * th)) @ q.conj().T
+    gates = [S.Gate(tuple(range(6)), M)]
+    U = O.block_matrix(m, gates)
+    u = Q.Unitary(gates, m)
+    u.eig()
+    r = u.eig_residual()
+    print("cluster of 70: residual %.3e" % r)
+    assert r <= 1e-10
+    _check_eig(u, U, 1e-9)
     u.free()
 
 
