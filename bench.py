@@ -217,8 +217,8 @@ def config2_modmul28(Q, S):
 
 def config3_mfma32(Q, S):
     """32 qubits complex64, depth-40 random circuit fused into blocks of up
-    to 6 qubits; 6-qubit blocks run on the FP32 matrix cores (real block
-    form, 512 N flop per launch). Per-block HIP events on the state's
+    to 6 qubits; 6- and 5-qubit blocks run on the FP32 matrix cores (real
+    block form, 512 N and 256 N flop per launch). Per-block HIP events on the state's
     stream give the matrix-core kernel's average launch time; the norm is
     accumulated in FP64. The same generator at 22 qubits (the twin) runs on
     the GPU in complex64 and on the FP64 oracle for the error."""
@@ -242,8 +242,10 @@ def config3_mfma32(Q, S):
     ms = np.array([evs[b].elapsed_time(evs[b + 1]) for b in range(nb)])
     nrm = st.norm2()
     mfma = [b for b in range(nb) if ks[b] == 6 and kinds[b] == Q.QS_BLOCK_DENSE]
+    mfma5 = [b for b in range(nb) if ks[b] == 5 and kinds[b] == Q.QS_BLOCK_DENSE]
     N = float(1 << n)
     t_mfma = float(np.mean(ms[mfma]))
+    t_mfma5 = float(np.mean(ms[mfma5])) if mfma5 else 0.0
     flop = 512.0 * N
     tflops = flop / (t_mfma * 1e-3) / 1e12
     prog.free()
@@ -260,15 +262,18 @@ def config3_mfma32(Q, S):
     err = float(np.abs(got - ref).max())
     rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     fid = float(abs(np.vdot(ref, got)) ** 2)
-    log("c3 32q c64 k=6: %d blocks (%d on matrix cores), %.2f ms per matrix-core launch (%.1f TFLOP/s), "
-        "twin err %.2e" % (nb, len(mfma), t_mfma, tflops, err))
+    log("c3 32q c64 k=6: %d blocks (%d 6-qubit and %d 5-qubit on matrix cores), %.2f ms per 6-qubit launch "
+        "(%.1f TFLOP/s), %.2f ms per 5-qubit launch, twin err %.2e" % (nb, len(mfma), len(mfma5), t_mfma, tflops,
+                                                                       t_mfma5, err))
     return {"n_qubits": n, "depth": depth, "fusion_k": k, "dtype": "c64", "blocks": nb,
             "mfma_blocks": len(mfma), "circuit_ms": round(float(ms.sum()), 2),
             "mfma_avg_launch_ms": round(t_mfma, 4),
+            "mfma5_blocks": len(mfma5), "mfma5_avg_launch_ms": round(t_mfma5, 4),
+            "mfma5_tflops": round(256.0 * N / (t_mfma5 * 1e-3) / 1e12, 2) if mfma5 else None,
             "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
                          "frac": round(tflops / 157.3, 4), "flop_per_launch": flop,
                          "hbm_gbs": round(2 * 8 * N / (t_mfma * 1e-3) / 1e9, 1),
-                         "kernel": "k_dense_mfma6 (v_mfma_f32_32x32x2f32, 6-qubit blocks)"},
+                         "kernel": "k_dense_mfma_pair<u64,6> (v_mfma_f32_32x32x2f32, 6-qubit blocks)"},
             "norm_fp64": nrm,
             "twin": {"n_qubits": nt, "max_abs_err": err, "rel_l2": rel, "fidelity": fid}}
 

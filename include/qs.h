@@ -561,12 +561,12 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *   QS_TUNE_SWEEP_PATH (dtype, k, class, n bucket): kernel for an
  *     uncontrolled dense k-qubit block: 1 thread per group (registers),
  *     2 wave tiles staged through LDS (needs n >= 6 + k; k <= 5 for
- *     complex128), 3 FP32 matrix cores (complex64, k = 6, n >= 12),
+ *     complex128), 3 FP32 matrix cores (complex64, k = 5 or 6, n >= 12),
  *     4 workgroup tiles with the output rows split over the waves (k >= 5,
  *     n >= 6 + k), 5 workgroup-shared 1024-amplitude tiles with one load
  *     per lane per tile row group (2 <= k <= 4, n >= 10). A path that does
  *     not apply to a block falls back to the default rule (matrix cores for
- *     complex64 k = 6, workgroup tiles for other blocks of 5 or 6 qubits,
+ *     complex64 k = 5 and 6, workgroup tiles for complex128 blocks of 5 or 6 qubits,
  *     shared 1024-amplitude tiles for complex128 blocks of 2 to 4 qubits on
  *     20 or more qubits, LDS below the line size, registers otherwise). Every path computes the same products; only the
  *     summation order of the FP32/FP64 dot products may differ.
@@ -577,8 +577,10 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     pass), 2..10.
  *   QS_TUNE_FFT_LDS_KB (dtype, -, -, n bucket): LDS tile budget of an FFT
  *     pass, 8..160 KiB (default 80: two workgroups per CU).
- *   QS_TUNE_MFMA_WG_PER_CU (complex64, k = 6, -, n bucket): persistent grid
- *     of the matrix-core sweep in workgroups per compute unit, 1..16.
+ *   QS_TUNE_MFMA_WG_PER_CU (complex64, k = 5 or 6, -, n bucket): persistent grid
+ *     of the matrix-core sweep in workgroups per compute unit, 1..16 (the
+ *     pair-layout kernels cap it at the number that fit; default: that
+ *     number, 4 for the real-form kernel).
  *   QS_TUNE_BATCH_GANG_SHARE (-, -, -, -): a batch circuit's gang is sized
  *     so its time per member is below 1/value of the average work per
  *     workgroup, 1..256.
@@ -601,6 +603,15 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     gather with 64 x 128 tiles in 1024-thread workgroups (default), 4
  *     with 64 x 64 tiles, 3 with 64 x 32, 2 with 64 x 16 (512 or 256
  *     threads), 1 the plain per-amplitude gather.
+ *   QS_TUNE_MFMA_KERNEL (complex64, k = 5 or 6, -, n bucket): matrix-core
+ *     sweep kernel: 0 or 3 the pair layout (tile staged once as (re, im)
+ *     pairs, four workgroups per compute unit, next tile loaded after the
+ *     outputs are staged; default), 2 the pair layout with the next tile
+ *     prefetched during the k loop (three workgroups per compute unit), 4
+ *     the pair layout loading each tile when it starts, 1 the real-form
+ *     layout (k = 6 only; two 32 KiB buffers, two workgroups per compute
+ *     unit). The pair-layout variants give identical results; the
+ *     real-form layout sums the same products in another order.
  *   QS_TUNE_GEMM_LIB (-, -, -, -): complex products of the dense-unitary
  *     route (squaring, controlled powers, the eigensolver route's
  *     products): 0 the library's own matrix-core kernel, 1 rocBLAS (a
@@ -614,7 +625,8 @@ enum qs_tune_param { QS_TUNE_SWEEP_PATH = 0, QS_TUNE_SWEEP_WG_PER_CU = 1, QS_TUN
                      QS_TUNE_FFT_LDS_KB = 3, QS_TUNE_MFMA_WG_PER_CU = 4,
                      QS_TUNE_BATCH_GANG_SHARE = 5, QS_TUNE_BATCH_BARRIER_AMPS = 6,
                      QS_TUNE_FFT_KERNEL = 7, QS_TUNE_SWEEP_NT = 8, QS_TUNE_FFT_NT = 9,
-                     QS_TUNE_GEMM_LIB = 10, QS_TUNE_MODMUL_KERNEL = 11, QS_TUNE_COUNT = 12 };
+                     QS_TUNE_GEMM_LIB = 10, QS_TUNE_MODMUL_KERNEL = 11, QS_TUNE_MFMA_KERNEL = 12,
+                     QS_TUNE_COUNT = 13 };
 /* Target classes: lowest target inside a 128-byte line, inside a wave's
  * 64 consecutive amplitudes, or above bit 5. */
 enum qs_tune_class { QS_TCLS_SUBLINE = 0, QS_TCLS_SUBWAVE = 1, QS_TCLS_HIGH = 2 };

@@ -102,7 +102,7 @@ def tune_sweep(timer, dtype, n, nb, reps, margin, log, rng):
         mat = random_unitary(k, rng)
         for cls in (Q.QS_TCLS_SUBLINE, Q.QS_TCLS_SUBWAVE, Q.QS_TCLS_HIGH):
             sets = class_targets(cls, k, n, dtype)
-            paths = [1, 2] + ([3] if dtype == Q.QS_C64 and k == 6 else []) + ([4] if k >= 5 else []) + \
+            paths = [1, 2] + ([3] if dtype == Q.QS_C64 and k >= 5 else []) + ([4] if k >= 5 else []) + \
                 ([5] if 2 <= k <= 4 else [])
             if dtype == Q.QS_C128 and k == 6:
                 paths = [1, 4]
@@ -204,6 +204,13 @@ def tune_mfma(timer, n, nb, reps, margin, log, rng):
         for t in sets:
             st.apply_gate(t, mat)
 
+    # kernel first (each at its own default grid), then the grid for it
+    ktimes = {}
+    for kern in (3, 2, 4, 1):
+        Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern, Q.QS_C64, 6, 0, nb)
+        ktimes[kern] = timer.ms(run_sets, reps)
+    kbest = _pick(ktimes, 3, margin)
+    Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kbest, Q.QS_C64, 6, 0, nb)
     times = {}
     for w in (1, 2, 3, 4, 6, 8):
         Q.tune_set(Q.QS_TUNE_MFMA_WG_PER_CU, w, Q.QS_C64, 6, 0, nb)
@@ -211,8 +218,11 @@ def tune_mfma(timer, n, nb, reps, margin, log, rng):
     st.free()
     best = _pick(times, 4, margin)
     Q.tune_set(Q.QS_TUNE_MFMA_WG_PER_CU, best, Q.QS_C64, 6, 0, nb)
-    log("mfma n=%d: %d WG/CU %s" % (n, best, {a: round(b, 3) for a, b in times.items()}))
-    return [{"param": "mfma_wg_per_cu", "dtype": Q.QS_C64, "k": 6, "cls": 0, "nbucket": nb, "value": int(best),
+    log("mfma n=%d: kernel %d %s, %d WG/CU %s" % (n, kbest, {a: round(b, 3) for a, b in ktimes.items()}, best,
+                                                 {a: round(b, 3) for a, b in times.items()}))
+    return [{"param": "mfma_kernel", "dtype": Q.QS_C64, "k": 6, "cls": 0, "nbucket": nb, "value": int(kbest),
+             "ms": {str(a): round(b, 4) for a, b in ktimes.items()}},
+            {"param": "mfma_wg_per_cu", "dtype": Q.QS_C64, "k": 6, "cls": 0, "nbucket": nb, "value": int(best),
              "ms": {str(a): round(b, 4) for a, b in times.items()}}]
 
 

@@ -9,18 +9,28 @@
 // ridge, so the FP32 MFMA units (v_mfma_f32_32x32x2_f32, FP32 inputs, FP32
 // accumulation) carry it.
 //
-// Workgroup: 4 waves, persistent over tiles of 64 groups (4096 amplitudes,
-// 32 KiB); the next tile is prefetched into registers during the MFMA loop. The tile spans index bits 0..5, the block qubits above bit 5 and
-// the lowest free bits above 5 (as many as there are block qubits below 6),
-// so loads and stores move 64 consecutive amplitudes per wave instruction;
-// an LDS layout switch regroups the tile into 64 columns of 64 amplitudes.
-// Wave w owns real output rows [32w, 32w+32) and keeps its 32 x 128 slice of
-// the real block matrix in 64 VGPRs for the whole kernel (A operand: lane l
-// holds row l%32 of the slice at k = 2s + l/32). For each half of the tile
-// (32 groups) it runs 64 MFMA steps over k; the B operand of step s is the
-// real-form element k = 2s + l/32 of group 32h + l%32, read from LDS.
-// Accumulator register v of lane l holds row 8(v/4) + 4(l/32) + v%4 of the
-// 32 x 32 output block and column l%32.
+// Both kernels: workgroups of 4 waves, persistent over tiles of 64 groups
+// (4096 amplitudes, 32 KiB). The tile spans index bits 0..5, the block
+// qubits above bit 5 and the lowest free bits above 5 (as many as there are
+// block qubits below 6), so loads and stores move 64 consecutive amplitudes
+// per wave instruction. Each wave keeps a 32 x 128 slice of the real block
+// matrix in 64 VGPRs for the whole kernel (A operand: lane l holds row l%32
+// of the slice at k = 2s + l/32), and runs 128 MFMA steps per tile over two
+// accumulators (groups 0..31 and 32..63). Accumulator register v of lane l
+// holds row 8(v/4) + 4(l/32) + v%4 of its 32 x 32 output block and column
+// l%32.
+//
+// k_dense_mfma6_pair (the default) stages the tile once, as (re, im) pairs
+// in a swizzled 32 KiB LDS layout with no bank conflicts; each wave owns the
+// real and imaginary rows of 16 outputs, so its results leave as pairs.
+// Four workgroups fit on a compute unit (113-121 VGPRs), and the next tile's
+// loads go out as soon as a tile's outputs are staged.
+//
+// k_dense_mfma6 (QS_TUNE_MFMA_KERNEL = 1) stages the tile in load order,
+// regroups it into a second 32 KiB buffer in real form and owns real output
+// rows [32w, 32w + 32) per wave; 194 VGPRs and 64 KiB LDS leave room for two
+// workgroups per compute unit, and the next tile is prefetched into
+// registers during the k loop.
 #include "qs_internal.h"
 
 #include <algorithm>
@@ -42,8 +52,8 @@ struct TileArgs {
     int bit0_pos;          // compact position of local bit 0
 };
 
-template <typename IT>
-__device__ __forceinline__ IT expand_tile(IT g, const TileArgs &ta)
+template <typename IT, typename Args>
+__device__ __forceinline__ IT expand_tile(IT g, const Args &ta)
 {
     for (int i = 0; i < ta.nfix; ++i) {
         const int p = ta.pos[i];
@@ -160,6 +170,150 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_dense_mfma6(float2 *__restri
     }
 }
 
+// Pair layout. The tile is staged in LDS once, as (re, im) pairs at
+// position (m << 6) | (col ^ sw(m)): m the block's local index (bit i of m is
+// the i-th lowest block qubit), col the group. sw(m) puts the bits of m that
+// come from block qubits below 6 back on those qubits' positions, so the
+// load-layout element of lane l lands at (m << 6) | (l ^ c_r): every staging
+// write and read moves 64 distinct bank pairs. Wave w owns the real and the
+// imaginary output rows of m in [16w, 16w + 16): local row i < 16 is Re y,
+// i >= 16 is Im y of m = 16w + (i & 15). Step s = 2t + p of the k loop takes
+// part p of input m = 2t + l/32, so one 8-byte LDS read feeds two steps, and
+// accumulator registers v and v + 8 hold the real and imaginary parts of one
+// output. The staging buffer is 32 KiB, which leaves room for three or four
+// workgroups per compute unit.
+struct PairArgs {
+    int nfix;
+    int pos[40];           // tile bit positions (ascending), removed from the tile index
+    uint64_t offl[64];     // global offset of load-layout register r (tile bits above 5)
+    uint32_t offr[64];     // LDS byte offset part of register r: ((m_r << 6) | c_r) * 8
+    uint32_t sw[64];       // swizzle of local index m, in bytes (sw(m) * 8)
+    int lane_m[6];         // local-index bit carried by lane bit b, or -1
+    int upos[6];           // position in the caller's target list of local bit i
+};
+
+// PF: 0 loads each tile when it starts, 1 prefetches the next tile into
+// registers during the k loop, 2 issues the next tile's loads after the
+// outputs are staged (into the accumulators' registers, free by then).
+template <typename IT, int K, int PF, int MINW>
+__global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_pair(float2 *__restrict__ psi,
+                                                                      const float *__restrict__ mat,
+                                                                      IT n_tiles, PairArgs pa)
+{
+    __shared__ float2 xs[4096];
+    char *xb = reinterpret_cast<char *>(xs);
+    auto lds = [&](int byte_off) -> float2 & { return *reinterpret_cast<float2 *>(xb + byte_off); };
+    // M local indices, 4096 / M groups per tile: CB column bits; wave w owns
+    // outputs [16 rb, 16 rb + 16) of the groups [64 ch, 64 ch + 64)
+    constexpr int M = 1 << K, NT = M / 2, CB = 12 - K, NRB = M / 16;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    const int hi = lane >> 5, lo = lane & 31;
+    const int rb = wave % NRB, ch = wave / NRB;
+
+    // A slice: output row i = lo of this wave, input (m = 2t + hi, part p)
+    // at step s = 2t + p
+    float a[2 * NT];
+    {
+        const int mo = 16 * rb + (lo & 15);
+        const bool oim = lo >= 16;
+        int uo = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b) uo |= ((mo >> b) & 1) << pa.upos[b];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int mi = 2 * t + hi;
+            int ui = 0;
+#pragma unroll
+            for (int b = 0; b < K; ++b) ui |= ((mi >> b) & 1) << pa.upos[b];
+            const float mr = mat[2 * (uo * M + ui)], mim = mat[2 * (uo * M + ui) + 1];
+            a[2 * t] = oim ? mim : mr;         // input real part
+            a[2 * t + 1] = oim ? mr : -mim;    // input imaginary part
+        }
+    }
+    // byte offsets (8 bytes per pair); staging position of this lane in the
+    // load layout: (m_l << CB) | l
+    int ml = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if (pa.lane_m[b] >= 0) ml |= ((lane >> b) & 1) << pa.lane_m[b];
+    const int base0 = ((ml << CB) | lane) << 3;
+    // B reads: pair (m = 2t + hi, col = 64ch + 32h + lo); sw is linear in m,
+    // so sw(2t + hi) = sw(2t) ^ sw(hi)
+    const int bl0 = (((hi << CB) | (64 * ch + lo)) << 3) ^ int(pa.sw[hi]);
+    // output writes: (m = 16rb + 8(v/4) + 4hi + v%4, col = 64ch + 32h + lo)
+    const int ol0 = ((((4 * hi) << CB) | (64 * ch + lo)) << 3) ^ int(pa.sw[4 * hi]);
+
+    // loaded amplitudes: pre (PF 0, 1) or, under PF 2, the accumulator
+    // registers, which are free between the staging of one tile's outputs
+    // and the next tile's k loop
+    float2 pre[16];
+    v16f acc[2] = {v16f{0}, v16f{0}};
+    auto put = [&](int q, float2 x) {
+        if (PF == 2) {
+            acc[q >> 3][(2 * q) & 15] = x.x;
+            acc[q >> 3][(2 * q + 1) & 15] = x.y;
+        } else {
+            pre[q] = x;
+        }
+    };
+    auto got = [&](int q) -> float2 {
+        if (PF == 2) return make_float2(acc[q >> 3][(2 * q) & 15], acc[q >> 3][(2 * q + 1) & 15]);
+        return pre[q];
+    };
+    auto fetch = [&](IT tt) {
+        const float2 *gs = psi + expand_tile<IT>(tt, pa) + lane;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) put(q, gs[pa.offl[16 * wave + q]]);
+    };
+    if (PF && IT(blockIdx.x) < n_tiles) fetch(IT(blockIdx.x));
+    for (IT t = IT(blockIdx.x); t < n_tiles; t += IT(gridDim.x)) {
+        float2 *g = psi + expand_tile<IT>(t, pa) + lane;
+        const bool more = t + IT(gridDim.x) < n_tiles;
+        if (!PF) fetch(t);
+        // the per-lane bases are made opaque once per tile, so the compiler
+        // recomputes the staging addresses instead of holding 100 of them
+        int base = base0, bl = bl0, ol = ol0;
+        asm volatile("" : "+v"(base), "+v"(bl), "+v"(ol));
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lds(base ^ int(pa.offr[16 * wave + q])) = got(q);
+        __syncthreads();
+        if (PF == 1 && more) fetch(t + IT(gridDim.x));   // each tile has one owner
+        acc[0] = v16f{0};
+        acc[1] = v16f{0};
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+            const int sx = int(pa.sw[2 * tt]);
+            const float2 b0 = lds((tt << (CB + 4)) + (bl ^ sx));
+            const float2 b1 = lds((tt << (CB + 4)) + ((bl ^ sx) ^ 256));
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2 * tt], b0.x, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2 * tt], b1.x, acc[1], 0, 0, 0);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2 * tt + 1], b0.y, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2 * tt + 1], b1.y, acc[1], 0, 0, 0);
+            if ((tt & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int mu = 16 * rb + 8 * (v >> 2) + (v & 3);   // m without its lane bit 2
+                lds((mu << (CB + 3)) + ((ol ^ int(pa.sw[mu])) ^ (256 * h))) = make_float2(acc[h][v], acc[h][v + 8]);
+            }
+        }
+        if (PF == 2) {
+            // keeps the loads after the staging writes, so the loaded
+            // values can take the accumulators' registers
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) fetch(t + IT(gridDim.x));
+        }
+        __syncthreads();
+#pragma unroll
+        // no barrier here: a wave reads back exactly the slots it fills with
+        // the next tile, so the next staging writes race with no other wave
+        for (int q = 0; q < 16; ++q) g[pa.offl[16 * wave + q]] = lds(base ^ int(pa.offr[16 * wave + q]));
+    }
+}
+
 template <typename IT>
 int launch_t(qs_state *h, const GateDesc &d, const float *dmat)
 {
@@ -209,17 +363,93 @@ int launch_t(qs_state *h, const GateDesc &d, const float *dmat)
     return QS_OK;
 }
 
+template <typename IT, int K, int PF, int MINW>
+int launch_pair_k(qs_state *h, const float *dmat, IT n_tiles, const PairArgs &pa)
+{
+    auto kern = k_dense_mfma_pair<IT, K, PF, MINW>;
+    int resident = 0;
+    QS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(kern), 64 * kWaves, 0));
+    const int per_cu = tune_value(QS_TUNE_MFMA_WG_PER_CU, QS_C64, K, 0, tune_nbucket(h->n));
+    const int wg = std::max(1, per_cu ? std::min(per_cu, resident) : resident);
+    const uint64_t grid = std::min<uint64_t>(uint64_t(n_tiles), uint64_t(device_cus()) * uint64_t(wg));
+    hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(64 * kWaves), 0, h->stream, static_cast<float2 *>(h->psi),
+                       dmat, n_tiles, pa);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+template <typename IT, int K>
+int launch_pair(qs_state *h, const GateDesc &d, const float *dmat, int variant)
+{
+    uint64_t tmask = 0;
+    for (int i = 0; i < K; ++i) tmask |= 1ull << d.targets[i];
+    std::vector<int> T(d.targets, d.targets + K);
+    std::sort(T.begin(), T.end());
+    int klo = 0;
+    for (int i = 0; i < K; ++i) klo += T[size_t(i)] < 6;
+    // the tile: bits 0..5, the block qubits above 5 and the lowest free bits
+    // above 5, 12 bits in all; the free bits carry the groups' remaining
+    // column bits (col bit T_i for the i-th of them while i < klo, then 6, 7)
+    std::vector<int> extra;
+    for (int b = 6; b < h->n && int(extra.size()) < 6 - (K - klo); ++b)
+        if (!((tmask >> b) & 1)) extra.push_back(b);
+    std::vector<int> P = {0, 1, 2, 3, 4, 5};
+    for (int i = klo; i < K; ++i) P.push_back(T[size_t(i)]);
+    for (int b : extra) P.push_back(b);
+    std::sort(P.begin(), P.end());
+    auto compact = [&](int b) { return int(std::lower_bound(P.begin(), P.end(), b) - P.begin()); };
+    constexpr int CB = 12 - K;
+    PairArgs pa;
+    pa.nfix = int(P.size());
+    for (int i = 0; i < pa.nfix; ++i) pa.pos[i] = P[size_t(i)];
+    for (int i = 0; i < 6; ++i)
+        pa.upos[i] = i < K ? int(std::find(d.targets, d.targets + K, T[size_t(i)]) - d.targets) : 0;
+    for (int r = 0; r < 64; ++r) {
+        uint64_t o = 0;
+        for (int i = 0; i < 6; ++i)
+            if ((r >> i) & 1) o |= 1ull << P[size_t(6 + i)];
+        pa.offl[r] = o;
+        uint32_t mr = 0, cr = 0;
+        for (int i = klo; i < K; ++i) mr |= uint32_t((r >> (compact(T[size_t(i)]) - 6)) & 1) << i;
+        for (int j = 0; j < int(extra.size()); ++j) {
+            const int cpos = j < klo ? T[size_t(j)] : 6 + (j - klo);
+            cr |= uint32_t((r >> (compact(extra[size_t(j)]) - 6)) & 1) << cpos;
+        }
+        pa.offr[r] = ((mr << CB) | cr) << 3;
+    }
+    for (int m = 0; m < 64; ++m) {
+        uint32_t sw = 0;
+        for (int i = 0; i < klo; ++i) sw |= uint32_t((m >> i) & 1) << T[size_t(i)];
+        pa.sw[m] = sw << 3;
+    }
+    for (int b = 0; b < 6; ++b) {
+        pa.lane_m[b] = -1;
+        for (int i = 0; i < klo; ++i)
+            if (T[size_t(i)] == b) pa.lane_m[b] = i;
+    }
+    const IT n_tiles = IT(h->dim() >> 12);
+    switch (variant) {
+    case 2: return launch_pair_k<IT, K, 1, 3>(h, dmat, n_tiles, pa);
+    case 4: return launch_pair_k<IT, K, 0, 4>(h, dmat, n_tiles, pa);
+    default: return launch_pair_k<IT, K, 2, 4>(h, dmat, n_tiles, pa);
+    }
+}
+
 }  // namespace
 
 bool mfma_applicable(const qs_state *h, const GateDesc &d)
 {
-    return h->dtype == QS_C64 && d.k == 6 && d.ctrl_mask == 0 && h->n >= 12;
+    return h->dtype == QS_C64 && (d.k == 5 || d.k == 6) && d.ctrl_mask == 0 && h->n >= 12;
 }
 
 int launch_dense_mfma(qs_state *h, const GateDesc &d, const void *dmat)
 {
     const float *m = static_cast<const float *>(dmat);
-    return h->n <= 31 ? launch_t<uint32_t>(h, d, m) : launch_t<uint64_t>(h, d, m);
+    const int variant = tune_value(QS_TUNE_MFMA_KERNEL, QS_C64, d.k, 0, tune_nbucket(h->n));
+    if (d.k == 5)
+        return h->n <= 31 ? launch_pair<uint32_t, 5>(h, d, m, variant) : launch_pair<uint64_t, 5>(h, d, m, variant);
+    if (variant == 1) return h->n <= 31 ? launch_t<uint32_t>(h, d, m) : launch_t<uint64_t>(h, d, m);
+    return h->n <= 31 ? launch_pair<uint32_t, 6>(h, d, m, variant) : launch_pair<uint64_t, 6>(h, d, m, variant);
 }
 
 }  // namespace qs

@@ -621,8 +621,9 @@ int dense_k(qs_state *h, const GateDesc &d, const void *dmat)
         if (wg_per_cu) g = std::min<uint64_t>(g, uint64_t(wg_per_cu) * uint64_t(device_cus()));
         return unsigned(std::max<uint64_t>(g, 1));
     };
-    // 6-qubit blocks on complex64 states: batched GEMM on the matrix cores
-    if constexpr (sizeof(R) == 4 && K == 6) {
+    // 5- and 6-qubit blocks on complex64 states: batched GEMM on the matrix
+    // cores
+    if constexpr (sizeof(R) == 4 && K >= 5) {
         if ((path == 0 || path == 3) && mfma_applicable(h, d)) return launch_dense_mfma(h, d, dmat);
     }
     // complex128 blocks of 2 to 4 qubits on states of 20 qubits or more

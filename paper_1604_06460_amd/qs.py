@@ -561,14 +561,14 @@ _sig("qs_tune_classify", [_I, _I, _I, _P, C.POINTER(_I), C.POINTER(_I)])
 
 (QS_TUNE_SWEEP_PATH, QS_TUNE_SWEEP_WG_PER_CU, QS_TUNE_FFT_DIGIT, QS_TUNE_FFT_LDS_KB,
  QS_TUNE_MFMA_WG_PER_CU, QS_TUNE_BATCH_GANG_SHARE, QS_TUNE_BATCH_BARRIER_AMPS, QS_TUNE_FFT_KERNEL,
- QS_TUNE_SWEEP_NT, QS_TUNE_FFT_NT, QS_TUNE_GEMM_LIB, QS_TUNE_MODMUL_KERNEL) = range(12)
+ QS_TUNE_SWEEP_NT, QS_TUNE_FFT_NT, QS_TUNE_GEMM_LIB, QS_TUNE_MODMUL_KERNEL, QS_TUNE_MFMA_KERNEL) = range(13)
 QS_TCLS_SUBLINE, QS_TCLS_SUBWAVE, QS_TCLS_HIGH = range(3)
 TUNE_PARAMS = {"sweep_path": QS_TUNE_SWEEP_PATH, "sweep_wg_per_cu": QS_TUNE_SWEEP_WG_PER_CU,
                "fft_digit": QS_TUNE_FFT_DIGIT, "fft_lds_kb": QS_TUNE_FFT_LDS_KB,
                "mfma_wg_per_cu": QS_TUNE_MFMA_WG_PER_CU, "batch_gang_share": QS_TUNE_BATCH_GANG_SHARE,
                "batch_barrier_amps": QS_TUNE_BATCH_BARRIER_AMPS, "fft_kernel": QS_TUNE_FFT_KERNEL,
                "sweep_nt": QS_TUNE_SWEEP_NT, "fft_nt": QS_TUNE_FFT_NT, "gemm_lib": QS_TUNE_GEMM_LIB,
-               "modmul_kernel": QS_TUNE_MODMUL_KERNEL}
+               "modmul_kernel": QS_TUNE_MODMUL_KERNEL, "mfma_kernel": QS_TUNE_MFMA_KERNEL}
 TUNED_FILE = os.path.join(_HERE, "tuned", "gfx950.json")
 
 

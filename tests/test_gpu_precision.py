@@ -39,13 +39,15 @@ def test_twin_22q_k6_complex64_vs_fp64_oracle(Q, O, S):
 
 
 def test_mfma_block_every_target_class(Q, O, S):
-    """6-qubit blocks on complex64 take the matrix-core path for low, high
-    and mixed targets."""
+    """6- and 5-qubit blocks on complex64 take the matrix-core path for low,
+    high and mixed targets."""
     rng = np.random.default_rng(12)
     n = 16
     for targets in ([0, 1, 2, 3, 4, 5], [10, 11, 12, 13, 14, 15], [0, 7, 3, 15, 9, 1],
-                    [6, 2, 13, 8, 11, 4]):
-        z = rng.standard_normal((64, 64)) + 1j * rng.standard_normal((64, 64))
+                    [6, 2, 13, 8, 11, 4], [0, 1, 2, 3, 4], [11, 12, 13, 14, 15], [0, 7, 3, 15, 9],
+                    [6, 2, 13, 8, 11]):
+        d = 1 << len(targets)
+        z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
         U = np.linalg.qr(z)[0]
         st = Q.State(n, Q.QS_C64)
         st.set(S.normal_state(n, 5))

@@ -149,6 +149,35 @@ def test_mfma_grid_sizes_match_oracle(Q, O, S):
         assert np.abs(got - ref).max() < TOL[0], w
 
 
+def test_every_mfma_kernel_matches_oracle(Q, O, S):
+    """Every matrix-core sweep variant (the two LDS layouts, with and
+    without register prefetch) against the oracle, for 6- and 5-qubit
+    blocks with targets below, above and across bit 6, given in ascending
+    and in scrambled order."""
+    n = 16
+    rng = np.random.default_rng(23)
+    psi0 = S.normal_state(n, 8)
+    cases = ([0, 1, 2, 3, 4, 5], [5, 3, 0, 1, 4, 2], [10, 11, 12, 13, 14, 15], [15, 6, 9, 12, 7, 10],
+             [0, 7, 3, 15, 9, 1], [6, 2, 13, 8, 11, 4], [5, 6, 7, 8, 9, 10], [1, 4, 6, 8, 9, 14],
+             [0, 1, 2, 3, 4], [4, 2, 0, 1, 3], [10, 11, 12, 13, 14], [2, 7, 12, 6, 1], [5, 6, 7, 8, 9],
+             [3, 9, 0, 15, 5], [6, 15, 8, 12, 10])
+    mats = [_unitary(len(t), rng) for t in cases]
+    refs = [O.apply_gate(psi0.copy(), t, m) for t, m in zip(cases, mats)]
+    try:
+        for kern in (1, 2, 3, 4):
+            Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern)
+            for t, m, ref in zip(cases, mats, refs):
+                st = Q.State(n, Q.QS_C64)
+                st.set(psi0)
+                st.apply_gate(t, m)
+                got = st.get().astype(np.complex128)
+                st.free()
+                err = float(np.abs(got - ref).max())
+                assert err < TOL[0], (kern, t, err)
+    finally:
+        Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, 0)
+
+
 def test_batch_gang_settings_give_identical_states(Q, S):
     circuits = S.batch_mix(24, 91, n_range=(12, 19), d_range=(3, 6), p_qft=0.3, p_modmul=0.3)
     b = Q.Batch(circuits)
