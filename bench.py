@@ -217,8 +217,10 @@ def config2_modmul28(Q, S):
 
 def config3_mfma32(Q, S):
     """32 qubits complex64, depth-40 random circuit fused into blocks of up
-    to 6 qubits; 6- and 5-qubit blocks run on the FP32 matrix cores (real
-    block form, 512 N and 256 N flop per launch). Per-block HIP events on the state's
+    to 6 qubits; 6- and 5-qubit blocks run on the FP32 matrix cores. The
+    complex work is 512 N and 256 N flop per launch (8 flop per complex
+    multiply-add); the three-product form executes 3/4 of it on the matrix
+    cores. Per-block HIP events on the state's
     stream give the matrix-core kernel's average launch time; the norm is
     accumulated in FP64. The same generator at 22 qubits (the twin) runs on
     the GPU in complex64 and on the FP64 oracle for the error."""
@@ -272,8 +274,11 @@ def config3_mfma32(Q, S):
             "mfma5_tflops": round(256.0 * N / (t_mfma5 * 1e-3) / 1e12, 2) if mfma5 else None,
             "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
                          "frac": round(tflops / 157.3, 4), "flop_per_launch": flop,
+                         "matrix_core_flop_per_launch": 0.75 * flop,
+                         "matrix_core_tflops": round(0.75 * tflops, 2),
                          "hbm_gbs": round(2 * 8 * N / (t_mfma * 1e-3) / 1e9, 1),
-                         "kernel": "k_dense_mfma_pair<u64,6> (v_mfma_f32_32x32x2f32, 6-qubit blocks)"},
+                         "kernel": "k_dense_mfma_3m<u64,6> (v_mfma_f32_16x16x4f32, 6-qubit blocks, three real "
+                                   "products per complex product)"},
             "norm_fp64": nrm,
             "twin": {"n_qubits": nt, "max_abs_err": err, "rel_l2": rel, "fidelity": fid}}
 

@@ -604,14 +604,17 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *     with 64 x 64 tiles, 3 with 64 x 32, 2 with 64 x 16 (512 or 256
  *     threads), 1 the plain per-amplitude gather.
  *   QS_TUNE_MFMA_KERNEL (complex64, k = 5 or 6, -, n bucket): matrix-core
- *     sweep kernel: 0 or 3 the pair layout (tile staged once as (re, im)
- *     pairs, four workgroups per compute unit, next tile loaded after the
- *     outputs are staged; default), 2 the pair layout with the next tile
- *     prefetched during the k loop (three workgroups per compute unit), 4
- *     the pair layout loading each tile when it starts, 1 the real-form
- *     layout (k = 6 only; two 32 KiB buffers, two workgroups per compute
- *     unit). The pair-layout variants give identical results; the
- *     real-form layout sums the same products in another order.
+ *     sweep kernel: 0 or 5 the three-product form (Re Y = Mr Xr - Mi Xi,
+ *     Im Y = (Mr + Mi)(Xr + Xi) - Mr Xr - Mi Xi: 3/4 of the matrix-core
+ *     work; default), 3 the real block form in the same pair layout (tile
+ *     staged once as (re, im) pairs, four workgroups per compute unit,
+ *     next tile loaded after the outputs are staged), 2 the same with the
+ *     next tile prefetched during the k loop (three workgroups per compute
+ *     unit), 4 the same loading each tile when it starts, 1 the real-form
+ *     layout (two 32 KiB buffers, two workgroups per compute unit; 6-qubit
+ *     blocks only, 5-qubit blocks take the default). Variants 2, 3 and 4 give identical results; the others sum
+ *     in other orders, and the three-product form rounds differently (its
+ *     imaginary part is a difference of products).
  *   QS_TUNE_GEMM_LIB (-, -, -, -): complex products of the dense-unitary
  *     route (squaring, controlled powers, the eigensolver route's
  *     products): 0 the library's own matrix-core kernel, 1 rocBLAS (a

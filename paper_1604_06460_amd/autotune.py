@@ -206,10 +206,10 @@ def tune_mfma(timer, n, nb, reps, margin, log, rng):
 
     # kernel first (each at its own default grid), then the grid for it
     ktimes = {}
-    for kern in (3, 2, 4, 1):
+    for kern in (5, 3, 2, 4, 1):
         Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern, Q.QS_C64, 6, 0, nb)
         ktimes[kern] = timer.ms(run_sets, reps)
-    kbest = _pick(ktimes, 3, margin)
+    kbest = _pick(ktimes, 5, margin)
     Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kbest, Q.QS_C64, 6, 0, nb)
     times = {}
     for w in (1, 2, 3, 4, 6, 8):

@@ -20,11 +20,14 @@
 // holds row 8(v/4) + 4(l/32) + v%4 of its 32 x 32 output block and column
 // l%32.
 //
-// k_dense_mfma6_pair (the default) stages the tile once, as (re, im) pairs
-// in a swizzled 32 KiB LDS layout with no bank conflicts; each wave owns the
-// real and imaginary rows of 16 outputs, so its results leave as pairs.
-// Four workgroups fit on a compute unit (113-121 VGPRs), and the next tile's
-// loads go out as soon as a tile's outputs are staged.
+// k_dense_mfma_3m (the default, 5- and 6-qubit blocks) and
+// k_dense_mfma_pair stage the tile once, as (re, im) pairs in a swizzled
+// 32 KiB LDS layout with no bank conflicts; each wave owns the real and
+// imaginary parts of 16 outputs, so its results leave as pairs. Four
+// workgroups fit on a compute unit, and the next tile's loads go out as
+// soon as a tile's outputs are staged. The pair kernel runs the real block
+// form; the three-product kernel forms Re and Im from three real products
+// (Gauss), 3/4 of the matrix-core work.
 //
 // k_dense_mfma6 (QS_TUNE_MFMA_KERNEL = 1) stages the tile in load order,
 // regroups it into a second 32 KiB buffer in real form and owns real output
@@ -314,6 +317,123 @@ __global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_pair(float2 *_
     }
 }
 
+// Three-product form (Gauss): with T1 = Mr Xr, T2 = Mi Xi and
+// T3 = (Mr + Mi)(Xr + Xi), Re Y = T1 - T2 and Im Y = T3 - T1 - T2: three real
+// products of 2^K x 2^K blocks where the real block form needs four, so the
+// matrix cores do 3/4 of the work. The tile is staged as in the pair layout
+// (sw additionally toggles column bit 4 with bit 0 of m unless the lowest
+// block qubit sits on bit 4, which keeps the 16-lane halves of every B read
+// on distinct banks). v_mfma_f32_16x16x4_f32: wave w owns outputs
+// [16 rb, 16 rb + 16) of the groups [64 ch, 64 ch + 64); lane l supplies A
+// row l%16 and B column l%16 at k = 4s + l/16, and accumulator register v of
+// lane l holds output row 4(l/16) + v. Each of the three products keeps four
+// 16-column accumulators; one 8-byte LDS read gives Xr, Xi and, added,
+// Xr + Xi for three MFMA steps.
+template <typename IT, int K, int MINW>
+__global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_3m(float2 *__restrict__ psi,
+                                                                   const float *__restrict__ mat, IT n_tiles,
+                                                                   PairArgs pa, int lane_ef)
+{
+    __shared__ float2 xs[4096];
+    char *xb = reinterpret_cast<char *>(xs);
+    auto lds = [&](int byte_off) -> float2 & { return *reinterpret_cast<float2 *>(xb + byte_off); };
+    constexpr int M = 1 << K, NS = M / 4, CB = 12 - K, NRB = M / 16;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int rb = wave % NRB, ch = wave / NRB;
+
+    float a1[NS], a2[NS], a3[NS];
+    {
+        const int mo = 16 * rb + c;
+        int uo = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b) uo |= ((mo >> b) & 1) << pa.upos[b];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int mi = 4 * s + g;
+            int ui = 0;
+#pragma unroll
+            for (int b = 0; b < K; ++b) ui |= ((mi >> b) & 1) << pa.upos[b];
+            const float mr = mat[2 * (uo * M + ui)], mim = mat[2 * (uo * M + ui) + 1];
+            a1[s] = mr;
+            a2[s] = mim;
+            a3[s] = mr + mim;
+        }
+    }
+    int ml = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if (pa.lane_m[b] >= 0) ml |= ((lane >> b) & 1) << pa.lane_m[b];
+    const int base0 = ((ml << CB) | (lane ^ (lane_ef ? (ml & 1) << 4 : 0))) << 3;
+    const int swg = ((g & 1) ? int(pa.sw[1]) : 0) ^ ((g & 2) ? int(pa.sw[2]) : 0);
+    const int sw4g = ((g & 1) ? int(pa.sw[4]) : 0) ^ ((g & 2) ? int(pa.sw[8]) : 0);
+    // B reads: pair (m = 4s + g, col = 64ch + 16cb + c)
+    const int bl0 = (((g << CB) | (64 * ch + c)) << 3) ^ swg;
+    // output writes: (m = 16rb + 4g + v, col = 64ch + 16cb + c)
+    const int ol0 = ((((4 * g) << CB) | (64 * ch + c)) << 3) ^ sw4g;
+
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f acc[3][4];
+    // the next tile's amplitudes are loaded into the first 32 accumulator
+    // registers once a tile's outputs are staged
+    auto put = [&](int q, float2 x) {
+        acc[q >> 3][(q >> 1) & 3][2 * (q & 1)] = x.x;
+        acc[q >> 3][(q >> 1) & 3][2 * (q & 1) + 1] = x.y;
+    };
+    auto got = [&](int q) -> float2 {
+        return make_float2(acc[q >> 3][(q >> 1) & 3][2 * (q & 1)], acc[q >> 3][(q >> 1) & 3][2 * (q & 1) + 1]);
+    };
+    auto fetch = [&](IT tt) {
+        const float2 *gs = psi + expand_tile<IT>(tt, pa) + lane;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) put(q, gs[pa.offl[16 * wave + q]]);
+    };
+    if (IT(blockIdx.x) < n_tiles) fetch(IT(blockIdx.x));
+    for (IT t = IT(blockIdx.x); t < n_tiles; t += IT(gridDim.x)) {
+        float2 *gp = psi + expand_tile<IT>(t, pa) + lane;
+        const bool more = t + IT(gridDim.x) < n_tiles;
+        int base = base0, bl = bl0, ol = ol0;
+        asm volatile("" : "+v"(base), "+v"(bl), "+v"(ol));
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lds(base ^ int(pa.offr[16 * wave + q])) = got(q);
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) acc[p][cb] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int sx = int(pa.sw[4 * s]);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const float2 b = lds((s << (CB + 5)) + ((bl ^ sx) ^ (cb << 7)));
+                acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b.x, acc[0][cb], 0, 0, 0);
+                acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[s], b.y, acc[1][cb], 0, 0, 0);
+                acc[2][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[s], b.x + b.y, acc[2][cb], 0, 0, 0);
+            }
+            if ((s & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int mu = 16 * rb + v;   // m without its lane bits 2, 3
+                const float t1 = acc[0][cb][v], t2 = acc[1][cb][v], t3 = acc[2][cb][v];
+                lds((mu << (CB + 3)) + ((ol ^ int(pa.sw[mu])) ^ (cb << 7))) = make_float2(t1 - t2, t3 - t1 - t2);
+            }
+        }
+        // loads after the staging writes, into the accumulators' registers
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) fetch(t + IT(gridDim.x));
+        __syncthreads();
+        // no barrier after this: a wave reads back exactly the slots it
+        // fills with the next tile
+#pragma unroll
+        for (int q = 0; q < 16; ++q) gp[pa.offl[16 * wave + q]] = lds(base ^ int(pa.offr[16 * wave + q]));
+    }
+}
+
 template <typename IT>
 int launch_t(qs_state *h, const GateDesc &d, const float *dmat)
 {
@@ -378,6 +498,21 @@ int launch_pair_k(qs_state *h, const float *dmat, IT n_tiles, const PairArgs &pa
     return QS_OK;
 }
 
+template <typename IT, int K, int MINW>
+int launch_3m_k(qs_state *h, const float *dmat, IT n_tiles, const PairArgs &pa, int lane_ef)
+{
+    auto kern = k_dense_mfma_3m<IT, K, MINW>;
+    int resident = 0;
+    QS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(kern), 64 * kWaves, 0));
+    const int per_cu = tune_value(QS_TUNE_MFMA_WG_PER_CU, QS_C64, K, 0, tune_nbucket(h->n));
+    const int wg = std::max(1, per_cu ? std::min(per_cu, resident) : resident);
+    const uint64_t grid = std::min<uint64_t>(uint64_t(n_tiles), uint64_t(device_cus()) * uint64_t(wg));
+    hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(64 * kWaves), 0, h->stream, static_cast<float2 *>(h->psi),
+                       dmat, n_tiles, pa, lane_ef);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
 template <typename IT, int K>
 int launch_pair(qs_state *h, const GateDesc &d, const float *dmat, int variant)
 {
@@ -417,11 +552,22 @@ int launch_pair(qs_state *h, const GateDesc &d, const float *dmat, int variant)
         }
         pa.offr[r] = ((mr << CB) | cr) << 3;
     }
-    for (int m = 0; m < 64; ++m) {
+    // the three-product kernel's swizzle also toggles column bit 4 with bit 0
+    // of m, unless the lowest block qubit is bit 4 itself
+    const bool three = !(variant == 2 || variant == 3 || variant == 4);   // the switch below
+    const bool ef = three && (klo == 0 || T[0] != 4);
+    auto swz = [&](int m) {
         uint32_t sw = 0;
         for (int i = 0; i < klo; ++i) sw |= uint32_t((m >> i) & 1) << T[size_t(i)];
-        pa.sw[m] = sw << 3;
-    }
+        if (ef) sw ^= uint32_t(m & 1) << 4;
+        return sw;
+    };
+    for (int m = 0; m < 64; ++m) pa.sw[m] = swz(m) << 3;
+    if (three)
+        for (int r = 0; r < 64; ++r) {
+            const uint32_t mr = (pa.offr[r] >> 3) >> CB;
+            pa.offr[r] ^= swz(int(mr)) << 3;
+        }
     for (int b = 0; b < 6; ++b) {
         pa.lane_m[b] = -1;
         for (int i = 0; i < klo; ++i)
@@ -430,8 +576,9 @@ int launch_pair(qs_state *h, const GateDesc &d, const float *dmat, int variant)
     const IT n_tiles = IT(h->dim() >> 12);
     switch (variant) {
     case 2: return launch_pair_k<IT, K, 1, 3>(h, dmat, n_tiles, pa);
+    case 3: return launch_pair_k<IT, K, 2, 4>(h, dmat, n_tiles, pa);
     case 4: return launch_pair_k<IT, K, 0, 4>(h, dmat, n_tiles, pa);
-    default: return launch_pair_k<IT, K, 2, 4>(h, dmat, n_tiles, pa);
+    default: return launch_3m_k<IT, K, 4>(h, dmat, n_tiles, pa, (klo >= 1 && T[0] != 4) ? 1 : 0);
     }
 }
 

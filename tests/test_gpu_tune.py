@@ -151,7 +151,8 @@ def test_mfma_grid_sizes_match_oracle(Q, O, S):
 
 def test_every_mfma_kernel_matches_oracle(Q, O, S):
     """Every matrix-core sweep variant (the two LDS layouts, with and
-    without register prefetch) against the oracle, for 6- and 5-qubit
+    without register prefetch, the three-product form) against the
+    oracle, for 6- and 5-qubit
     blocks with targets below, above and across bit 6, given in ascending
     and in scrambled order."""
     n = 16
@@ -164,7 +165,7 @@ def test_every_mfma_kernel_matches_oracle(Q, O, S):
     mats = [_unitary(len(t), rng) for t in cases]
     refs = [O.apply_gate(psi0.copy(), t, m) for t, m in zip(cases, mats)]
     try:
-        for kern in (1, 2, 3, 4):
+        for kern in (1, 2, 3, 4, 5):
             Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern)
             for t, m, ref in zip(cases, mats, refs):
                 st = Q.State(n, Q.QS_C64)
