@@ -116,3 +116,45 @@ def test_28q_modmul_configuration_full_state_bit_exact(Q, O, S):
     st.free()
     ref = O.modmul(psi, 0, 20, 20, 8, a, Nmod)
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+
+
+@pytest.mark.parametrize("targets", [[26, 3, 17, 31, 0, 9], [12, 13, 14, 15, 16, 17], [5, 4, 3, 2, 1, 0],
+                                     [31, 2, 20, 7, 11], [0, 1, 2, 3, 4]])
+def test_32q_matrix_core_block_sampled_vs_oracle(Q, O, S, targets):
+    """The 32-qubit complex64 matrix-core sweep (64-bit tile indices, the
+    tuned kernel and grid that bench.py's 32-qubit circuit runs) on a
+    random state: sampled outputs against the oracle applied to each
+    sample's group of 2^k input amplitudes, read from the state before the
+    block."""
+    import torch
+    n, k = 32, len(targets)
+    rng = np.random.default_rng(S.SEED_BASE + 37 + k)
+    z = rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+    U = np.linalg.qr(z)[0]
+    gen = torch.Generator(device="cuda").manual_seed(1604 + sum(targets))
+    x = torch.randn(2 << n, generator=gen, dtype=torch.float32, device="cuda")
+    x.mul_(2.0 ** (-(n + 1) / 2))
+    st = Q.State(n, Q.QS_C64)
+    st.load_device(x.data_ptr())
+    st.sync()
+    del x
+    torch.cuda.empty_cache()
+    out_idx = _sample(n, 192, 40 + k)
+    tmask = sum(1 << t for t in targets)
+    local = np.arange(1 << k, dtype=np.uint64)
+    offs = np.zeros(1 << k, dtype=np.uint64)
+    for i, t in enumerate(targets):
+        offs |= ((local >> np.uint64(i)) & np.uint64(1)) << np.uint64(t)
+    base = out_idx & ~np.uint64(tmask)
+    groups = base[:, None] | offs[None, :]
+    inputs = st.amplitudes(groups.reshape(-1)).astype(np.complex128).reshape(len(out_idx), 1 << k)
+    st.apply_gate(targets, U)
+    got = st.amplitudes(out_idx).astype(np.complex128)
+    st.free()
+    torch.cuda.empty_cache()
+    ref = np.empty(len(out_idx), dtype=np.complex128)
+    for s in range(len(out_idx)):
+        i_out = sum(((int(out_idx[s]) >> t) & 1) << i for i, t in enumerate(targets))
+        ref[s] = O.apply_gate(inputs[s].copy(), list(range(k)), U)[i_out]
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() < 1e-5 * scale, (targets, np.abs(got - ref).max(), scale)
