@@ -179,6 +179,33 @@ def test_every_mfma_kernel_matches_oracle(Q, O, S):
         Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, 0)
 
 
+def test_mfma_kernels_on_one_and_two_tiles(Q, O, S):
+    """The smallest states the matrix-core path takes: 12 qubits (one
+    4096-amplitude tile, a grid of one workgroup) and 13 qubits (two
+    tiles), for 5- and 6-qubit blocks whose targets fill the tile or leave
+    it the fewest free bits, in every kernel variant."""
+    rng = np.random.default_rng(29)
+    cases = [(12, [6, 7, 8, 9, 10, 11]), (12, [0, 11, 5, 6, 2, 9]), (12, [0, 1, 2, 3, 4, 5]),
+             (12, [7, 8, 9, 10, 11]), (12, [4, 0, 11, 3, 1]), (13, [12, 6, 7, 8, 9, 10]),
+             (13, [0, 1, 2, 3, 4]), (13, [12, 11, 10, 9, 8])]
+    try:
+        for n, t in cases:
+            psi0 = S.normal_state(n, 3 + n)
+            m = _unitary(len(t), rng)
+            ref = O.apply_gate(psi0.copy(), t, m)
+            for kern in (1, 2, 3, 4, 5):
+                Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern)
+                st = Q.State(n, Q.QS_C64)
+                st.set(psi0)
+                st.apply_gate(t, m)
+                got = st.get().astype(np.complex128)
+                st.free()
+                err = float(np.abs(got - ref).max())
+                assert err < TOL[0], (n, t, kern, err)
+    finally:
+        Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, 0)
+
+
 def test_batch_gang_settings_give_identical_states(Q, S):
     circuits = S.batch_mix(24, 91, n_range=(12, 19), d_range=(3, 6), p_qft=0.3, p_modmul=0.3)
     b = Q.Batch(circuits)
