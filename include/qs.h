@@ -606,7 +606,9 @@ int qs_apply_qpe_eig(qs_handle h, qs_unitary u, int ctrl_lo, int b);
  *   QS_TUNE_MFMA_KERNEL (complex64, k = 5 or 6, -, n bucket): matrix-core
  *     sweep kernel: 0 or 5 the three-product form (Re Y = Mr Xr - Mi Xi,
  *     Im Y = (Mr + Mi)(Xr + Xi) - Mr Xr - Mi Xi: 3/4 of the matrix-core
- *     work; default), 3 the real block form in the same pair layout (tile
+ *     work; default; 16-byte accesses of two neighbouring amplitudes unless
+ *     qubit 0 is a block qubit), 6 the same with 8-byte accesses, 3 the
+ *     real block form in the same pair layout (tile
  *     staged once as (re, im) pairs, four workgroups per compute unit,
  *     next tile loaded after the outputs are staged), 2 the same with the
  *     next tile prefetched during the k loop (three workgroups per compute

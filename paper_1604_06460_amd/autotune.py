@@ -206,7 +206,7 @@ def tune_mfma(timer, n, nb, reps, margin, log, rng):
 
     # kernel first (each at its own default grid), then the grid for it
     ktimes = {}
-    for kern in (5, 3, 2, 4, 1):
+    for kern in (5, 6, 3, 2, 4, 1):
         Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern, Q.QS_C64, 6, 0, nb)
         ktimes[kern] = timer.ms(run_sets, reps)
     kbest = _pick(ktimes, 5, margin)

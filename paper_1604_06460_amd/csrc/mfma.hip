@@ -328,8 +328,10 @@ __global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_pair(float2 *_
 // row l%16 and B column l%16 at k = 4s + l/16, and accumulator register v of
 // lane l holds output row 4(l/16) + v. Each of the three products keeps four
 // 16-column accumulators; one 8-byte LDS read gives Xr, Xi and, added,
-// Xr + Xi for three MFMA steps.
-template <typename IT, int K, int MINW>
+// Xr + Xi for three MFMA steps. With W16 (qubit 0 not in the block) a lane
+// moves two neighbouring amplitudes per global access, halving the vector
+// memory instructions of a tile.
+template <typename IT, int K, int MINW, bool W16>
 __global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_3m(float2 *__restrict__ psi,
                                                                    const float *__restrict__ mat, IT n_tiles,
                                                                    PairArgs pa, int lane_ef)
@@ -360,11 +362,18 @@ __global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_3m(float2 *__r
             a3[s] = mr + mim;
         }
     }
+    // W16: a lane moves two neighbouring amplitudes (16 bytes) of row
+    // 16w + 2q + l/32 at positions pl, pl + 1; bit 0 is then no block qubit,
+    // so the two share m and land in adjacent LDS slots
+    // (offl and offr are linear in r, so row 2q + 1 adds offl[1] and
+    // toggles offr[1]: folded into the lane's base address and slot)
+    const int pl = W16 ? 2 * (lane & 31) : lane, hrow = W16 ? lane >> 5 : 0;
     int ml = 0;
 #pragma unroll
     for (int b = 0; b < 6; ++b)
-        if (pa.lane_m[b] >= 0) ml |= ((lane >> b) & 1) << pa.lane_m[b];
-    const int base0 = ((ml << CB) | (lane ^ (lane_ef ? (ml & 1) << 4 : 0))) << 3;
+        if (pa.lane_m[b] >= 0) ml |= ((pl >> b) & 1) << pa.lane_m[b];
+    const int base0 = (((ml << CB) | (pl ^ (lane_ef ? (ml & 1) << 4 : 0))) << 3) ^ (hrow ? int(pa.offr[1]) : 0);
+    const uint64_t hoff = hrow ? pa.offl[1] : 0;
     const int swg = ((g & 1) ? int(pa.sw[1]) : 0) ^ ((g & 2) ? int(pa.sw[2]) : 0);
     const int sw4g = ((g & 1) ? int(pa.sw[4]) : 0) ^ ((g & 2) ? int(pa.sw[8]) : 0);
     // B reads: pair (m = 4s + g, col = 64ch + 16cb + c)
@@ -383,19 +392,35 @@ __global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_3m(float2 *__r
     auto got = [&](int q) -> float2 {
         return make_float2(acc[q >> 3][(q >> 1) & 3][2 * (q & 1)], acc[q >> 3][(q >> 1) & 3][2 * (q & 1) + 1]);
     };
+    auto put4 = [&](int q, float4 x) { acc[q >> 2][q & 3] = v4f{x.x, x.y, x.z, x.w}; };
+    auto got4 = [&](int q) -> float4 {
+        const v4f a = acc[q >> 2][q & 3];
+        return make_float4(a[0], a[1], a[2], a[3]);
+    };
     auto fetch = [&](IT tt) {
-        const float2 *gs = psi + expand_tile<IT>(tt, pa) + lane;
+        const float2 *gs = psi + expand_tile<IT>(tt, pa) + pl + hoff;
+        if constexpr (W16) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) put(q, gs[pa.offl[16 * wave + q]]);
+            for (int q = 0; q < 8; ++q) put4(q, *reinterpret_cast<const float4 *>(gs + pa.offl[16 * wave + 2 * q]));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) put(q, gs[pa.offl[16 * wave + q]]);
+        }
     };
     if (IT(blockIdx.x) < n_tiles) fetch(IT(blockIdx.x));
     for (IT t = IT(blockIdx.x); t < n_tiles; t += IT(gridDim.x)) {
-        float2 *gp = psi + expand_tile<IT>(t, pa) + lane;
+        float2 *gp = psi + expand_tile<IT>(t, pa) + pl + hoff;
         const bool more = t + IT(gridDim.x) < n_tiles;
         int base = base0, bl = bl0, ol = ol0;
         asm volatile("" : "+v"(base), "+v"(bl), "+v"(ol));
+        if constexpr (W16) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) lds(base ^ int(pa.offr[16 * wave + q])) = got(q);
+            for (int q = 0; q < 8; ++q)
+                *reinterpret_cast<float4 *>(xb + (base ^ int(pa.offr[16 * wave + 2 * q]))) = got4(q);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) lds(base ^ int(pa.offr[16 * wave + q])) = got(q);
+        }
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < 3; ++p)
@@ -429,8 +454,15 @@ __global__ __launch_bounds__(64 * kWaves, MINW) void k_dense_mfma_3m(float2 *__r
         __syncthreads();
         // no barrier after this: a wave reads back exactly the slots it
         // fills with the next tile
+        if constexpr (W16) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) gp[pa.offl[16 * wave + q]] = lds(base ^ int(pa.offr[16 * wave + q]));
+            for (int q = 0; q < 8; ++q)
+                *reinterpret_cast<float4 *>(gp + pa.offl[16 * wave + 2 * q]) =
+                    *reinterpret_cast<const float4 *>(xb + (base ^ int(pa.offr[16 * wave + 2 * q])));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) gp[pa.offl[16 * wave + q]] = lds(base ^ int(pa.offr[16 * wave + q]));
+        }
     }
 }
 
@@ -498,10 +530,10 @@ int launch_pair_k(qs_state *h, const float *dmat, IT n_tiles, const PairArgs &pa
     return QS_OK;
 }
 
-template <typename IT, int K, int MINW>
+template <typename IT, int K, int MINW, bool W16>
 int launch_3m_k(qs_state *h, const float *dmat, IT n_tiles, const PairArgs &pa, int lane_ef)
 {
-    auto kern = k_dense_mfma_3m<IT, K, MINW>;
+    auto kern = k_dense_mfma_3m<IT, K, MINW, W16>;
     int resident = 0;
     QS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(kern), 64 * kWaves, 0));
     const int per_cu = tune_value(QS_TUNE_MFMA_WG_PER_CU, QS_C64, K, 0, tune_nbucket(h->n));
@@ -578,7 +610,11 @@ int launch_pair(qs_state *h, const GateDesc &d, const float *dmat, int variant)
     case 2: return launch_pair_k<IT, K, 1, 3>(h, dmat, n_tiles, pa);
     case 3: return launch_pair_k<IT, K, 2, 4>(h, dmat, n_tiles, pa);
     case 4: return launch_pair_k<IT, K, 0, 4>(h, dmat, n_tiles, pa);
-    default: return launch_3m_k<IT, K, 4>(h, dmat, n_tiles, pa, (klo >= 1 && T[0] != 4) ? 1 : 0);
+    case 6: return launch_3m_k<IT, K, 4, false>(h, dmat, n_tiles, pa, (klo >= 1 && T[0] != 4) ? 1 : 0);
+    default:
+        // 16-byte accesses unless bit 0 is a block qubit
+        if (T[0] != 0) return launch_3m_k<IT, K, 4, true>(h, dmat, n_tiles, pa, (klo >= 1 && T[0] != 4) ? 1 : 0);
+        return launch_3m_k<IT, K, 4, false>(h, dmat, n_tiles, pa, (klo >= 1 && T[0] != 4) ? 1 : 0);
     }
 }
 

@@ -37,7 +37,7 @@ Range range_of(int p)
     case QS_TUNE_FFT_NT: return {1, 3};
     case QS_TUNE_GEMM_LIB: return {1, 1};
     case QS_TUNE_MODMUL_KERNEL: return {1, 5};
-    case QS_TUNE_MFMA_KERNEL: return {1, 5};
+    case QS_TUNE_MFMA_KERNEL: return {1, 6};
     default: return {0, -1};
     }
 }

@@ -165,7 +165,7 @@ def test_every_mfma_kernel_matches_oracle(Q, O, S):
     mats = [_unitary(len(t), rng) for t in cases]
     refs = [O.apply_gate(psi0.copy(), t, m) for t, m in zip(cases, mats)]
     try:
-        for kern in (1, 2, 3, 4, 5):
+        for kern in (1, 2, 3, 4, 5, 6):
             Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern)
             for t, m, ref in zip(cases, mats, refs):
                 st = Q.State(n, Q.QS_C64)
@@ -193,7 +193,7 @@ def test_mfma_kernels_on_one_and_two_tiles(Q, O, S):
             psi0 = S.normal_state(n, 3 + n)
             m = _unitary(len(t), rng)
             ref = O.apply_gate(psi0.copy(), t, m)
-            for kern in (1, 2, 3, 4, 5):
+            for kern in (1, 2, 3, 4, 5, 6):
                 Q.tune_set(Q.QS_TUNE_MFMA_KERNEL, kern)
                 st = Q.State(n, Q.QS_C64)
                 st.set(psi0)
