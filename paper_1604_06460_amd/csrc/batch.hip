@@ -180,6 +180,109 @@ __device__ void op_dense(float2 *st, int n, const BOp &op, const float *__restri
     }
 }
 
+// 5- and 6-qubit blocks on states in HBM (14 qubits or more) run on the
+// FP32 matrix cores as three real products per complex product:
+// Re Y = Mr Xr - Mi Xi, Im Y = (Mr + Mi)(Xr + Xi) - Mr Xr - Mi Xi, over
+// tiles of 4096 amplitudes (the block's qubits and the 12 - K lowest other
+// bits, which number the C = 4096 / 2^K columns). A tile is staged in the
+// dynamic LDS, m-major with rows of C + 16 pairs, so that the two 16-lane
+// halves of every B read fall on distinct banks; outputs go straight back
+// to HBM. Wave w owns outputs [16 rb, 16 rb + 16) of the columns
+// [64 ch, 64 ch + 64), in two passes of 32 columns; v_mfma_f32_16x16x4_f32,
+// lane l supplying A row l%16 and B column l%16 at k = 4s + l/16, and
+// holding output rows 4(l/16) + v of its 16-column block.
+__device__ __forceinline__ uint32_t pdep_bits(uint32_t x, uint32_t mask, int nbits)
+{
+    uint32_t o = 0;
+    for (int i = 0; i < nbits; ++i) {
+        const uint32_t low = mask & (0u - mask);
+        if ((x >> i) & 1u) o |= low;
+        mask ^= low;
+    }
+    return o;
+}
+
+template <int K>
+__device__ void op_dense_mfma(float2 *st, int n, const BOp &op, const float *__restrict__ mat, uint32_t r,
+                              uint32_t G, float2 *xs)
+{
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    constexpr int M = 1 << K, NS = M / 4, C = 4096 / M, NRB = M / 16, PAD = C + 16, NF = 12 - K;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int rb = wave % NRB, ch = wave / NRB;
+    uint32_t tmask = 0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) tmask |= 1u << op.t[m];
+    uint32_t fmask = 0;                       // the NF lowest bits outside the block
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const uint32_t x = tmask | fmask;
+        fmask |= ~x & (x + 1u);
+    }
+    const uint32_t tile_mask = tmask | fmask;
+    auto mbits = [&](int m) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) o |= uint32_t((m >> i) & 1) << op.t[i];
+        return o;
+    };
+    float a1[NS], a2[NS], a3[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int idx = 2 * ((16 * rb + c) * M + 4 * s + g);
+        a1[s] = mat[idx];
+        a2[s] = mat[idx + 1];
+        a3[s] = a1[s] + a2[s];
+    }
+    const uint32_t mg4 = mbits(4 * g);
+    // staging: thread tid takes column tid % C of rows tid / C + (256 / C) q
+    const uint32_t scol = threadIdx.x % C, srow = threadIdx.x / C, scoff = pdep_bits(scol, fmask, NF);
+    const uint32_t n_tiles = 1u << (n - 12);
+    for (uint32_t tt = r; tt < n_tiles; tt += G) {
+        uint32_t tb = tt;
+        for (uint32_t msk = tile_mask; msk; msk &= msk - 1u) {
+            const int p = __builtin_ctz(msk);
+            tb = ((tb >> p) << (p + 1)) | (tb & ((1u << p) - 1u));
+        }
+#pragma unroll 4
+        for (int q = 0; q < 4096 / kBT; ++q) {
+            const int m = int(srow) + (kBT / C) * q;
+            xs[m * PAD + int(scol)] = st[tb | scoff | mbits(m)];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int half = 0; half < 2; ++half) {
+            v4f acc[3][2];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[p][h] = v4f{0.f, 0.f, 0.f, 0.f};
+            const int col0 = 64 * ch + 32 * half + c;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float2 b = xs[(4 * s + g) * PAD + col0 + 16 * h];
+                    acc[0][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b.x, acc[0][h], 0, 0, 0);
+                    acc[1][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[s], b.y, acc[1][h], 0, 0, 0);
+                    acc[2][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[s], b.x + b.y, acc[2][h], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t co = tb | pdep_bits(uint32_t(col0 + 16 * h), fmask, NF) | mg4;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float t1 = acc[0][h][v], t2 = acc[1][h][v], t3 = acc[2][h][v];
+                    st[co | mbits(16 * rb + v)] = float2{t1 - t2, t3 - t1 - t2};
+                }
+            }
+        }
+        __syncthreads();   // every wave is done with the staged tile
+    }
+}
+
 __device__ void op_diag(float2 *st, int n, const BOp &op, const float *__restrict__ mat, uint32_t r, uint32_t G)
 {
     const int D = 1 << op.k;
@@ -343,6 +446,12 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2
                 break;
             case OP_DENSE: {
                 const float *m = pool + op.mat;
+                if (op.k >= 5 && !in_lds) {
+                    float2 *xs = reinterpret_cast<float2 *>(lds_raw);   // staging: the LDS no HBM state uses
+                    if (op.k == 5) op_dense_mfma<5>(dst, cc.n, op, m, r, G, xs);
+                    else op_dense_mfma<6>(dst, cc.n, op, m, r, G, xs);
+                    break;
+                }
                 switch (op.k) {
                 case 1: op_dense<1>(dst, cc.n, op, m, r, G); break;
                 case 2: op_dense<2>(dst, cc.n, op, m, r, G); break;
