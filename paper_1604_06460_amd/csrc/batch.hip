@@ -55,6 +55,7 @@ struct BOp {
     int64_t mat;        // offset in floats into the FP32 matrix pool
     int q_lo, m, inv;   // FFT field
     int pass;           // index into the pass table
+    int mono;           // OP_DENSE: the block is a monomial (moves and phases), swept exactly on the ALUs
     int work_lo, w, ctrl_lo, c;
     uint32_t N, pad;
     uint64_t a, mu;
@@ -180,8 +181,9 @@ __device__ void op_dense(float2 *st, int n, const BOp &op, const float *__restri
     }
 }
 
-// 5- and 6-qubit blocks on states in HBM (14 qubits or more) run on the
-// FP32 matrix cores as three real products per complex product:
+// Dense 4- to 6-qubit blocks on states in HBM (14 qubits or more) run on
+// the FP32 matrix cores as three real products per complex product (blocks
+// of moves and phases stay on the ALUs, whose one-term sums are exact):
 // Re Y = Mr Xr - Mi Xi, Im Y = (Mr + Mi)(Xr + Xi) - Mr Xr - Mi Xi, over
 // tiles of 4096 amplitudes (the block's qubits and the 12 - K lowest other
 // bits, which number the C = 4096 / 2^K columns). A tile is staged in the
@@ -446,9 +448,10 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(float2 *__restrict__ A, float2
                 break;
             case OP_DENSE: {
                 const float *m = pool + op.mat;
-                if (op.k >= 5 && !in_lds) {
+                if (op.k >= 4 && !in_lds && !op.mono) {
                     float2 *xs = reinterpret_cast<float2 *>(lds_raw);   // staging: the LDS no HBM state uses
-                    if (op.k == 5) op_dense_mfma<5>(dst, cc.n, op, m, r, G, xs);
+                    if (op.k == 4) op_dense_mfma<4>(dst, cc.n, op, m, r, G, xs);
+                    else if (op.k == 5) op_dense_mfma<5>(dst, cc.n, op, m, r, G, xs);
                     else op_dense_mfma<6>(dst, cc.n, op, m, r, G, xs);
                     break;
                 }
@@ -577,7 +580,7 @@ struct SegInfo {
 struct FusedList {       // a gate list fused at some k, composed into the pool
     std::vector<int> blk_k;
     std::vector<std::vector<int>> blk_q;
-    std::vector<int> blk_diag;
+    std::vector<int> blk_diag, blk_mono;
     std::vector<int64_t> blk_mat;   // pool offset (floats)
 };
 
@@ -783,7 +786,7 @@ int compose_lists(qs_batch_t *b, const std::vector<std::pair<int, int>> &need)
             ComposeBlock B;
             B.k = kb;
             B.g0 = int(cg.size());
-            bool diag = true;
+            bool diag = true, mono = true;
             for (int g : p.block_gates[bi]) {
                 ComposeGate G;
                 std::memset(&G, 0, sizeof G);
@@ -800,6 +803,8 @@ int compose_lists(qs_batch_t *b, const std::vector<std::pair<int, int>> &need)
                 GateDesc tmp;
                 classify(src, G.k, tmp);
                 if (!(tmp.cls == GC_IDENTITY || tmp.cls == GC_PHASE1 || tmp.cls == GC_DIAG)) diag = false;
+                if (!(tmp.cls == GC_IDENTITY || tmp.cls == GC_PHASE1 || tmp.cls == GC_DIAG || tmp.cls == GC_MONOMIAL))
+                    mono = false;
                 cg.push_back(G);
             }
             B.g1 = int(cg.size());
@@ -809,6 +814,7 @@ int compose_lists(qs_batch_t *b, const std::vector<std::pair<int, int>> &need)
             F.blk_k.push_back(kb);
             F.blk_q.push_back(qs);
             F.blk_diag.push_back(diag ? 1 : 0);
+            F.blk_mono.push_back(mono ? 1 : 0);
             F.blk_mat.push_back(int64_t(b->pool_floats) + out_off);
             out_off += int64_t(2) << (2 * kb);
         }
@@ -1069,6 +1075,7 @@ int qs_batch_set_plan(qs_batch b, const int *options)
                     BOp op;
                     std::memset(&op, 0, sizeof op);
                     op.type = F.blk_diag[bi] ? OP_DIAG : OP_DENSE;
+                    op.mono = F.blk_mono[bi];
                     op.k = F.blk_k[bi];
                     op.seg = sid;
                     op.src = op.dst = cur;
