@@ -72,11 +72,15 @@ def test_batch_plans_match_oracle(Q, S, small_batch, refs, rule):
     b.free()
 
 
-def test_modmul_gate_level_and_emulated_bit_identical(Q, S, small_batch):
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_modmul_gate_level_and_emulated_bit_identical(Q, S, small_batch, fuse):
+    """Fused at k = 4 or 6, a gate-level modular multiplication's blocks are
+    monomials (moves and phases), which stay on the exact ALU op also in
+    circuits whose other dense blocks run on the matrix cores."""
     b = Q.Batch(small_batch)
-    kinds, _, _ = b.segment_info()
-    assert (kinds == 2).any()
-    base = _options(kinds, 1)          # every segment fused at k=4
+    kinds, _, nq = b.segment_info()
+    assert (kinds == 2).any() and (nq[kinds == 2] >= 14).any()
+    base = _options(kinds, fuse)       # every segment fused at k = 4 (1) or 6 (2)
     emu = base.copy()
     emu[kinds == 2] = 3                # modmul emulated
     b.set_plan(base)
