@@ -1,39 +1,39 @@
-// Fused 6-qubit blocks on complex64 states as a batched GEMM on the matrix
-// cores. A sweep computes Y = M X for every group X of 64 amplitudes that
-// agree outside the block's qubits (the Kronecker structure of Sec. II). In
-// real block form
+// Fused 5- and 6-qubit blocks on complex64 states as a batched GEMM on the
+// matrix cores. A sweep computes Y = M X for every group X of 2^k
+// amplitudes that agree outside the block's qubits (the Kronecker structure
+// of Sec. II). In real block form
 //   [Yr]   [Mr  -Mi] [Xr]
 //   [Yi] = [Mi   Mr] [Xi]
-// this is a 128 x 128 real matrix times 128 x G real columns, with 8 flops
-// per complex multiply-add, 32 flop per byte moved: past the FP32 vector
-// ridge, so the FP32 MFMA units (v_mfma_f32_32x32x2_f32, FP32 inputs, FP32
+// a 6-qubit block is a 128 x 128 real matrix times 128 x G real columns,
+// 8 flops per complex multiply-add and 32 flop per byte moved: past the
+// FP32 vector ridge, so the FP32 MFMA units (FP32 inputs, FP32
 // accumulation) carry it.
 //
-// Both kernels: workgroups of 4 waves, persistent over tiles of 64 groups
-// (4096 amplitudes, 32 KiB). The tile spans index bits 0..5, the block
-// qubits above bit 5 and the lowest free bits above 5 (as many as there are
-// block qubits below 6), so loads and stores move 64 consecutive amplitudes
-// per wave instruction. Each wave keeps a 32 x 128 slice of the real block
-// matrix in 64 VGPRs for the whole kernel (A operand: lane l holds row l%32
-// of the slice at k = 2s + l/32), and runs 128 MFMA steps per tile over two
-// accumulators (groups 0..31 and 32..63). Accumulator register v of lane l
-// holds row 8(v/4) + 4(l/32) + v%4 of its 32 x 32 output block and column
-// l%32.
+// Every kernel here: workgroups of 4 waves, persistent over tiles of 4096
+// amplitudes (32 KiB). A tile spans index bits 0..5, the block qubits above
+// bit 5 and the lowest free bits above 5 (12 bits in all), so loads and
+// stores move runs of 64 consecutive amplitudes per wave instruction. Each
+// wave keeps its slice of the block matrix in registers for the whole
+// kernel.
 //
-// k_dense_mfma_3m (the default, 5- and 6-qubit blocks) and
-// k_dense_mfma_pair stage the tile once, as (re, im) pairs in a swizzled
-// 32 KiB LDS layout with no bank conflicts; each wave owns the real and
-// imaginary parts of 16 outputs, so its results leave as pairs. Four
-// workgroups fit on a compute unit, and the next tile's loads go out as
-// soon as a tile's outputs are staged. The pair kernel runs the real block
-// form; the three-product kernel forms Re and Im from three real products
-// (Gauss), 3/4 of the matrix-core work.
+// k_dense_mfma_3m (the default) forms Re Y = Mr Xr - Mi Xi and
+// Im Y = (Mr + Mi)(Xr + Xi) - Mr Xr - Mi Xi from three real products
+// (Gauss), 3/4 of the real block form's matrix-core work, on
+// v_mfma_f32_16x16x4_f32. k_dense_mfma_pair runs the real block form on
+// v_mfma_f32_32x32x2_f32. Both stage the tile once, as (re, im) pairs in a
+// swizzled 32 KiB LDS layout with no bank conflicts; each wave owns the real
+// and imaginary parts of 16 outputs, so its results leave as pairs. Four
+// workgroups fit on a compute unit, and the next tile's loads go out as soon
+// as a tile's outputs are staged.
 //
-// k_dense_mfma6 (QS_TUNE_MFMA_KERNEL = 1) stages the tile in load order,
-// regroups it into a second 32 KiB buffer in real form and owns real output
-// rows [32w, 32w + 32) per wave; 194 VGPRs and 64 KiB LDS leave room for two
-// workgroups per compute unit, and the next tile is prefetched into
-// registers during the k loop.
+// k_dense_mfma6 (QS_TUNE_MFMA_KERNEL = 1, 6-qubit blocks) is the first
+// layout: it stages the tile in load order, regroups it into a second
+// 32 KiB buffer in real form and owns real output rows [32w, 32w + 32) per
+// wave (a 32 x 128 slice of the real block matrix in 64 VGPRs; A operand:
+// lane l holds row l%32 at k = 2s + l/32; accumulator register v of lane l
+// holds row 8(v/4) + 4(l/32) + v%4 and column l%32 of its 32 x 32 output
+// block); 194 VGPRs and 64 KiB LDS leave room for two workgroups per compute
+// unit, and the next tile is prefetched into registers during the k loop.
 #include "qs_internal.h"
 
 #include <algorithm>
