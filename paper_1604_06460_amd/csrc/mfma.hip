@@ -174,17 +174,19 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_dense_mfma6(float2 *__restri
 }
 
 // Pair layout. The tile is staged in LDS once, as (re, im) pairs at
-// position (m << 6) | (col ^ sw(m)): m the block's local index (bit i of m is
-// the i-th lowest block qubit), col the group. sw(m) puts the bits of m that
-// come from block qubits below 6 back on those qubits' positions, so the
-// load-layout element of lane l lands at (m << 6) | (l ^ c_r): every staging
-// write and read moves 64 distinct bank pairs. Wave w owns the real and the
-// imaginary output rows of m in [16w, 16w + 16): local row i < 16 is Re y,
-// i >= 16 is Im y of m = 16w + (i & 15). Step s = 2t + p of the k loop takes
-// part p of input m = 2t + l/32, so one 8-byte LDS read feeds two steps, and
-// accumulator registers v and v + 8 hold the real and imaginary parts of one
-// output. The staging buffer is 32 KiB, which leaves room for three or four
-// workgroups per compute unit.
+// position (m << CB) | (col ^ sw(m)): m the block's local index (bit i of m
+// is the i-th lowest block qubit), col the group (CB = 12 - k column bits).
+// sw(m) puts the bits of m that come from block qubits below 6 back on those
+// qubits' positions, so the load-layout element of lane l lands at
+// (m << CB) | (l ^ c_r): every staging write and read moves 64 distinct bank
+// pairs. Wave w owns the real and the imaginary output rows of m in
+// [16 rb, 16 rb + 16) for the groups [64 ch, 64 ch + 64) (rb = w, ch = 0 for
+// 6-qubit blocks; rb = w % 2, ch = w / 2 for 5-qubit blocks): local row
+// i < 16 is Re y, i >= 16 is Im y of m = 16 rb + (i & 15). Step s = 2t + p of
+// the k loop takes part p of input m = 2t + l/32, so one 8-byte LDS read
+// feeds two steps, and accumulator registers v and v + 8 hold the real and
+// imaginary parts of one output. The staging buffer is 32 KiB, which leaves
+// room for three or four workgroups per compute unit.
 struct PairArgs {
     int nfix;
     int pos[40];           // tile bit positions (ascending), removed from the tile index
